@@ -1,0 +1,223 @@
+"""FP64 CPU oracle of the focus+context hex-mesh render path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The product path (the HIP library
+and its Python binding) never imports it, and it never imports them.
+
+The arithmetic lives in ``hexfc_oracle.c`` (plain C, FP64, exact integer
+geometry); this file only marshals numpy arrays.  Build it with
+``oracle.build()`` (gcc, OpenMP).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hexfc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# style vector layout shared with hexfc_oracle.c (ST_* enum)
+STYLE_FIELDS = ("w_base", "k_focus", "halo_width", "halo_alpha", "darken", "accent_s",
+                "accent_brighten", "delta", "lod")
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ct.CDLL(_LIB)
+    P = ct.c_void_p
+    i64 = ct.c_int64
+    lib.orc_mesh_build.argtypes = [P, i64, P, i64, P, P, ct.POINTER(P)]
+    lib.orc_mesh_build.restype = ct.c_int
+    lib.orc_mesh_free.argtypes = [P]
+    lib.orc_mesh_sizes.argtypes = [P, P]
+    lib.orc_mesh_export.argtypes = [P, P, P, P, P, P, P]
+    lib.orc_scaled_jacobian.argtypes = [P]
+    lib.orc_scaled_jacobian.restype = ct.c_double
+    lib.orc_smoothstep.argtypes = [ct.c_double, ct.c_double, ct.c_double]
+    lib.orc_smoothstep.restype = ct.c_double
+    lib.orc_frame_raster.argtypes = [P, P, ct.c_int, ct.c_int, i64, P, ct.POINTER(P)]
+    lib.orc_frame_raster.restype = ct.c_int
+    lib.orc_frame_free.argtypes = [P]
+    lib.orc_frame_nfrag.argtypes = [P]
+    lib.orc_frame_nfrag.restype = i64
+    lib.orc_frame_lists.argtypes = [P, P, P, P]
+    lib.orc_frame_vertices.argtypes = [P, P, P, P, P]
+    lib.orc_frame_shade.argtypes = [P, P, P, P, P]
+    lib.orc_frame_shade.restype = ct.c_int
+    lib.orc_frame_ncand.argtypes = [P]
+    lib.orc_frame_ncand.restype = i64
+    lib.orc_frame_cands.argtypes = [P, P, P]
+    lib.orc_shade_one.argtypes = [P, i64, i64, ct.c_uint32, P, P, ct.c_uint, P]
+    lib.orc_num_threads.restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def style_vector(st) -> np.ndarray:
+    """Pack a synth.Style (or anything with the same attributes) into the
+    oracle's 20-double style vector."""
+    v = [float(getattr(st, k)) for k in STYLE_FIELDS]
+    v += [float(x) for x in st.tf_rgb_lo] + [float(x) for x in st.tf_rgb_hi]
+    v += [float(st.tf_a_lo), float(st.tf_a_hi)] + [float(x) for x in st.bg]
+    return np.asarray(v, dtype=np.float64)
+
+
+def hotspot_vector(h) -> np.ndarray:
+    return np.asarray(list(h.center) + [h.radius], dtype=np.float64)
+
+
+def scaled_jacobian(corners) -> float:
+    c = np.ascontiguousarray(np.asarray(corners, dtype=np.float64).reshape(8, 3))
+    return float(_load().orc_scaled_jacobian(_ptr(c)))
+
+
+def smoothstep(e0, e1, x) -> float:
+    return float(_load().orc_smoothstep(e0, e1, x))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Mesh:
+    """Oracle-side mesh attributes (positions quantised, importance, faces)."""
+
+    def __init__(self, xyz, hex, cell_scalar=None, cell_edge_level=None):
+        lib = _load()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+        self._hex = np.ascontiguousarray(hex, dtype=np.int32)
+        self._sc = None if cell_scalar is None else np.ascontiguousarray(cell_scalar, dtype=np.float32)
+        self._lv = None if cell_edge_level is None else np.ascontiguousarray(cell_edge_level, dtype=np.uint8)
+        h = ct.c_void_p()
+        rc = lib.orc_mesh_build(_ptr(self._xyz), self._xyz.shape[0], _ptr(self._hex), self._hex.shape[0],
+                                _ptr(self._sc), _ptr(self._lv), ct.byref(h))
+        if rc != 0:
+            raise OracleError(f"orc_mesh_build failed: {rc}")
+        self._h = h
+        sizes = np.zeros(3, dtype=np.int64)
+        lib.orc_mesh_sizes(h, _ptr(sizes))
+        self.V, self.C, self.F = (int(x) for x in sizes)
+
+    @classmethod
+    def from_synth(cls, m):
+        return cls(m.xyz, m.hex, m.cell_scalar, m.cell_edge_level)
+
+    def export(self):
+        V, C, F = self.V, self.C, self.F
+        out = dict(pos_q=np.zeros((V, 3), np.int32), t_cell=np.zeros(C), t_v=np.zeros(V),
+                   face_v=np.zeros((F, 4), np.int32), face_lvl=np.zeros((F, 4), np.uint8),
+                   face_te=np.zeros((F, 4)))
+        _load().orc_mesh_export(self._h, *(_ptr(out[k]) for k in
+                                           ("pos_q", "t_cell", "t_v", "face_v", "face_lvl", "face_te")))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().orc_mesh_free(self._h)
+            self._h = None
+
+
+class Frame:
+    """One camera's exact fragment lists over a set of sample pixels."""
+
+    def __init__(self, mesh: Mesh, view_proj, width: int, height: int, pixels=None):
+        lib = _load()
+        self.mesh = mesh
+        self.W, self.H = int(width), int(height)
+        vp = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+        self._pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
+        h = ct.c_void_p()
+        n = 0 if self._pix is None else self._pix.size
+        rc = lib.orc_frame_raster(mesh._h, _ptr(vp), self.W, self.H, n, _ptr(self._pix), ct.byref(h))
+        if rc != 0:
+            raise OracleError(f"orc_frame_raster failed: {rc}")
+        self._h = h
+        self.npix = self.W * self.H if self._pix is None else self._pix.size
+        self.nfrag = int(lib.orc_frame_nfrag(h))
+
+    @classmethod
+    def from_camera(cls, mesh, cam, pixels=None):
+        return cls(mesh, cam.view_proj, cam.width, cam.height, pixels)
+
+    def lists(self):
+        """(count u32[npix], off u64[npix+1], rec u64[F]) with every list sorted."""
+        count = np.zeros(self.npix, np.uint32)
+        off = np.zeros(self.npix + 1, np.uint64)
+        rec = np.zeros(self.nfrag, np.uint64)
+        _load().orc_frame_lists(self._h, _ptr(count), _ptr(off), _ptr(rec))
+        return count, off, rec
+
+    def vertices(self):
+        V = self.mesh.V
+        sx, sy, q = (np.zeros(V, np.int32) for _ in range(3))
+        fl = np.zeros(V, np.uint8)
+        _load().orc_frame_vertices(self._h, _ptr(sx), _ptr(sy), _ptr(q), _ptr(fl))
+        return sx, sy, q, fl
+
+    def shade(self, hotspot, style):
+        """FP64 RGBA per sample pixel plus the alternative results of pixels
+        whose fragments sit on a discontinuity within FP32 error:
+        returns (rgba [npix,4], ncand [npix], cand_off [npix+1], cand [n,4])."""
+        lib = _load()
+        hv = hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot
+        sv = style_vector(style) if not isinstance(style, np.ndarray) else style
+        hv = np.ascontiguousarray(hv, np.float64)
+        sv = np.ascontiguousarray(sv, np.float64)
+        rgba = np.zeros((self.npix, 4))
+        ncand = np.zeros(self.npix, np.int32)
+        rc = lib.orc_frame_shade(self._h, _ptr(hv), _ptr(sv), _ptr(rgba), _ptr(ncand))
+        if rc != 0:
+            raise OracleError(f"orc_frame_shade failed: {rc}")
+        nc = int(lib.orc_frame_ncand(self._h))
+        cand_off = np.zeros(self.npix + 1, np.int64)
+        cand = np.zeros((nc, 4))
+        lib.orc_frame_cands(self._h, _ptr(cand_off), _ptr(cand))
+        return rgba, ncand, cand_off, cand
+
+    def shade_one(self, i, j, tri, hotspot, style, flip=0):
+        hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
+        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        out = np.zeros(5)
+        _load().orc_shade_one(self._h, int(i), int(j), int(tri), _ptr(hv), _ptr(sv), int(flip), _ptr(out))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().orc_frame_free(self._h)
+            self._h = None
+
+
+def render(mesh_synth, cam, hot, style, pixels=None):
+    """Convenience: full oracle pass for one view.  Returns a dict."""
+    om = Mesh.from_synth(mesh_synth)
+    fr = Frame.from_camera(om, cam, pixels)
+    count, off, rec = fr.lists()
+    rgba, ncand, cand_off, cand = fr.shade(hot, style)
+    return dict(mesh=om, frame=fr, count=count, off=off, rec=rec, rgba=rgba, ncand=ncand,
+                cand_off=cand_off, cand=cand)
