@@ -1,0 +1,167 @@
+"""Benchmark: focus+context hex-mesh frames at 1080p on one MI355X.
+
+Workload: a 128^3-cell hex grid through a smooth bend with 5% strongly
+sheared 4^3-cell blocks (2,097,152 cells, 6,340,608 faces), 1920x1080, the
+16 orbit cameras with their moving spherical hotspots, 8 GB fragment
+workspace.  One step = one whole frame (transform, bin, count, scan, fill,
+sort + shade + blend) for the next camera.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 32] [--warmup 4] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(mesh, cam, hot, style, row_step: int):
+    """Time the FP64 oracle (as it stands) on every `row_step`-th row of one view."""
+    import numpy as np
+
+    import oracle
+    W, H = cam.width, cam.height
+    rows = np.arange(0, H, row_step)
+    pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int32)
+    om = oracle.Mesh.from_synth(mesh)
+    t0 = time.perf_counter()
+    fr = oracle.Frame.from_camera(om, cam, pixels=pix)
+    fr.shade(hot, style)
+    dt = time.perf_counter() - t0
+    return dict(value=fr.nfrag / dt, unit="fragments/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"view 0, every {row_step}th row ({pix.size} of {W * H} pixels, {fr.nfrag} fragments), "
+                       f"{dt:.1f} s; mesh attribute preprocessing excluded",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-row-step", type=int, default=8)
+    ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the screen-space split across GPUs is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2009_06574_amd as hx
+    import synth
+
+    hx.load()
+    t0 = time.perf_counter()
+    if args.grid == 128:
+        mesh, cams, hots, styles = synth.config2()
+    else:
+        mesh, cams, hots, styles = synth.scaled_config(args.grid, 1920, 1080, "bent")
+    log(f"[bench] mesh {mesh.name}: {mesh.V} vertices, {mesh.C} cells ({time.perf_counter() - t0:.1f} s)")
+    r = hx.Renderer(0)
+    r.set_workspace(8 << 30)
+    t0 = time.perf_counter()
+    r.upload(mesh)
+    log(f"[bench] upload {time.perf_counter() - t0:.1f} s")
+    out = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    nv = len(cams)
+    for i in range(args.warmup):
+        r.render(cams[i % nv], hots[i % nv], styles[i % nv], out=out)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} frames)")
+    r.set_profiling(True)
+    r.kernel_times()
+    frags = 0
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        k = (args.warmup + i) % nv
+        r.render(cams[k], hots[k], styles[k], out=out)
+        st = r.frame_stats()
+        frags += st["fragments"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = r.kernel_times()
+    r.set_profiling(False)
+    ms_frame = 1000.0 * dt / args.steps
+    log(f"[bench] {args.steps} frames in {dt:.3f} s: {ms_frame:.3f} ms/frame, {frags / dt / 1e9:.3f} G fragments/s")
+
+    # roofline of the dominant list kernel (fill or a resolve class), from the
+    # HIP events recorded around its launches on the render stream
+    P = 1920 * 1080
+    sum_cls_f = np.zeros(8)
+    sum_cls_p = np.zeros(8)
+    bins = 0
+    for st in stats:
+        sum_cls_f += np.asarray(st["class_fragments"], dtype=np.float64)
+        sum_cls_p += np.asarray(st["classes"], dtype=np.float64)
+        bins += st["bins"]
+    alg = {}
+    if "fill" in kt:
+        alg["fill"] = 8.0 * frags + 4.0 * bins + 8.0 * P * args.steps
+    for c in range(7):
+        k = f"resolve_c{c}"
+        if k in kt:
+            alg[k] = 8.0 * sum_cls_f[c] + 32.0 * sum_cls_p[c]
+    dom = max(alg, key=lambda k: kt[k][0])
+    ms_dom, n_dom = kt[dom]
+    achieved = (alg[dom] / n_dom) / (ms_dom / n_dom * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom,
+                    avg_launch_ms=round(ms_dom / n_dom, 4),
+                    bytes_per_launch=int(alg[dom] / n_dom))
+    kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
+    log(f"[bench] per-frame kernel ms: {kernel_ms}")
+    log(f"[bench] dominant {dom}: {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(mesh, cams[0], hots[0], styles[0], args.cpu_row_step)
+        log(f"[bench] oracle {cpu['value'] / 1e6:.2f} M fragments/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+        cpu.pop("seconds")
+
+    line = {
+        "metric": "ms/frame & fragments/s at 1080p; exact vs learned-tail resolve at >=45 dB PSNR",
+        "value": frags / dt,
+        "unit": "fragments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_frame,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"bent+sheared {args.grid}^3 hex grid, 1920x1080, 16 orbit views, exact resolve",
+                   "cells": mesh.C, "faces": 3 * args.grid * args.grid * (args.grid + 1),
+                   "fragments_per_frame": frags / args.steps, "workspace_GB": 8},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"kernel_ms_per_frame": kernel_ms,
+                   "paper_context": "cubic128 (2,097,152 cells) at 1920x1080 on an RTX 2070 SUPER: "
+                                    "147.3 ms/frame (45.8 F+C + 101.5 PPFL), other mesh and hardware"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * hexfc.h -- C ABI of the MI355X (gfx950) focus+context hex-mesh renderer.
+ *
+ * Implements the per-frame path of Neuhauser, Wang, Westermann,
+ * "Interactive Focus+Context Rendering for Hexahedral Mesh Inspection"
+ * (arXiv 2009.06574): every hexahedral face is rasterised as two triangles
+ * (Section 4), each pixel's fragments are kept in a per-pixel list, sorted by
+ * distance to the camera and alpha-blended front to back (Section 3,
+ * Section 6), each fragment being shaded by the focus+context rules of
+ * Eq. 1-4 (Section 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status:     every call returns a hexfc_status; no C++ exception crosses the
+ *             ABI; hexfc_last_error() gives a human-readable detail.  A failed
+ *             call leaves the previously uploaded mesh and built lists intact.
+ * Streams:    `stream` is a hipStream_t passed as void* (NULL = the default
+ *             stream).  Work is enqueued on it; device outputs are valid once
+ *             the stream has been synchronised.
+ * Memory:     the context owns its device copy of the mesh and its internal
+ *             scratch (bins, counts, offsets).  The fragment workspace
+ *             (hexfc_set_workspace) and every *_out device buffer belong to
+ *             the caller.  Host input arrays are only read during the call.
+ * Threads:    a context is used by one host thread at a time.
+ * Devices:    a context is bound to the device given to hexfc_create; every
+ *             device pointer passed to it must live on that device.
+ *
+ * Integer geometry contract (identical results on every device)
+ * ------------------------------------------------------------
+ * positions   X_q = rint(x * 2^16), |x| < 4 world units
+ * camera      M_q = rint(M * 2^20), |M_ij| < 8; rows 0, 1 and 3 of the
+ *             row-major world->clip matrix are used (clip w = row 3)
+ * screen      4 sub-pixel bits; pixel (i, j) (row j from the top) has its
+ *             centre at sub-pixel (16 i + 8, 16 j + 8)
+ * culling     a triangle is dropped if a vertex has w < 1/16 or lies outside
+ *             the guard band |s| < 2^17 sub-pixels, or if its snapped area is 0
+ * fill rule   half-open: a centre on an edge belongs to the triangle whose
+ *             interior lies on the side of (+eps, +eps*delta)
+ * depth key   q = floor(2^56 / w_q); key = floor(sum E_i q_i / sum E_i) with
+ *             the edge functions E_i of the pixel centre (exact inverse-depth
+ *             interpolation); record = ((2^24 - key) << 32) | triangle id,
+ *             triangle id = 2 * face + {0: (c0,c1,c2), 1: (c0,c2,c3)};
+ *             lists are sorted ascending (front to back, ties by face id).
+ */
+#ifndef HEXFC_H
+#define HEXFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hexfc_status {
+    HEXFC_OK = 0,
+    HEXFC_EINVAL = -1,    /* malformed argument or inconsistent mesh data     */
+    HEXFC_ERANGE = -2,    /* value outside the documented limits               */
+    HEXFC_ENOMEM = -3,    /* device or host allocation failed                  */
+    HEXFC_EOVERFLOW = -4, /* fragments do not fit the workspace / a list limit */
+    HEXFC_EDEVICE = -5,   /* a HIP runtime call failed                         */
+    HEXFC_ESTATE = -6     /* call order violated (no mesh, no lists, ...)      */
+} hexfc_status;
+
+typedef struct hexfc_ctx hexfc_ctx;
+
+/* Camera: row-major float world->clip matrix and viewport (1..8192 each). */
+typedef struct hexfc_camera {
+    float view_proj[16];
+    int32_t width, height;
+} hexfc_camera;
+
+/* Focus region: an object-space sphere (the paper's object-space lens,
+ * Section 4 / Section 8): dist = |p - center| / radius, focus =
+ * 1 - smoothstep(0.7, 1, dist).  radius > 0. */
+typedef struct hexfc_hotspot {
+    float center[3];
+    float radius;
+} hexfc_hotspot;
+
+/* Live shading constants (Section 6: constant shader parameters).
+ *   w_base          minimum edge width in world units (Eq. 1)
+ *   k_focus         width gain in focus, w = (1 + k_focus*focus) w_base (Eq. 1)
+ *   halo_width      halo band beyond w in focus, scaled by focus (Section 4)
+ *   halo_alpha      halo opacity (white halo)
+ *   darken          focus-edge darkening: C_F *= 1 - darken*focus
+ *   accent_s        accentuation factor s of Eq. 2
+ *   accent_brighten face-colour gain on accentuated fragments (Section 4.2)
+ *   delta           importance threshold of Eq. 1
+ *   lod             LoD threshold of Eq. 1 (edge visible in context iff level >= lod)
+ *   tf_*            transfer function: colour lerp(lo, hi, t), opacity lerp(a_lo, a_hi, t)
+ *   bg              background colour behind the composite (Section 4.1) */
+typedef struct hexfc_style {
+    float w_base, k_focus, halo_width, halo_alpha, darken;
+    float accent_s, accent_brighten, delta;
+    int32_t lod;
+    float tf_rgb_lo[3], tf_rgb_hi[3];
+    float tf_a_lo, tf_a_hi;
+    float bg[3];
+} hexfc_style;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+hexfc_status hexfc_create(int device, hexfc_ctx **out);
+
+/* Release the context and every device buffer it owns (NULL is a no-op). */
+void hexfc_destroy(hexfc_ctx *ctx);
+
+/* Fragment workspace: caller-owned device memory of `bytes` bytes (8 bytes per
+ * fragment record).  A frame whose fragments exceed it is rendered in several
+ * screen passes (Section 7: subdividing the screen), each of which must fit;
+ * hexfc_build_fragment_lists needs the whole frame to fit.  The pointer must
+ * be 256-byte aligned.  Passing NULL/0 detaches the workspace. */
+hexfc_status hexfc_set_workspace(hexfc_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Upload a hexahedral mesh (Section 3 / Section 6: all render data resident on
+ * the GPU).  Host arrays:
+ *   xyz              float [V][3] vertex positions, |x| < 4
+ *   hex              int32 [C][8] corner ids, VTK hexahedron order
+ *   cell_scalar      float [C] per-cell importance source, or NULL for
+ *                    1 - scaled Jacobian (min over the 8 corners, Section 3);
+ *                    normalised to [0,1] over the mesh
+ *   cell_edge_level  uint8 [C][12] LoD level of each local cell edge
+ *                    (0:(0,1) 1:(1,2) 2:(2,3) 3:(3,0) 4:(4,5) 5:(5,6) 6:(6,7)
+ *                    7:(7,4) 8:(0,4) 9:(1,5) 10:(2,6) 11:(3,7)), or NULL (all 0)
+ * Vertex importance = max over incident cells, edge importance = max over
+ * cells sharing the edge (Section 3).  Faces are deduplicated in first-seen
+ * order.  Errors: EINVAL (bad sizes, a repeated corner, cells that disagree
+ * on a shared edge's level), ERANGE (|x| >= 4, ids out of range, V >= 2^31,
+ * more than 2^31 - 1 triangles). */
+hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, const int32_t *hex,
+                               int64_t C, const float *cell_scalar, const uint8_t *cell_edge_level);
+
+/* Build the per-pixel fragment lists of one view (Section 6): transform and
+ * snap, bin triangles to screen tiles, count, prefix-scan, fill.  The lists
+ * stay in the workspace for hexfc_resolve / hexfc_export_sorted_lists; they
+ * do not depend on hotspot or style.  counts_out: optional device uint32
+ * [height][width] fragment count per pixel.  Synchronises `stream` once to
+ * size its buffers.  Errors: ESTATE (no mesh / no workspace), ERANGE (camera
+ * limits), EOVERFLOW (the frame does not fit the workspace). */
+hexfc_status hexfc_build_fragment_lists(hexfc_ctx *ctx, const hexfc_camera *cam,
+                                        uint32_t *counts_out, void *stream);
+
+/* Resolve the last built lists: sort each pixel's list front to back, shade
+ * every fragment (Eq. 1-4) and composite (Section 4.2) over the background.
+ * rgba_out: device float [height][width][4], premultiplied colour plus
+ * accumulated opacity.  Errors: ESTATE (no lists), EINVAL (radius <= 0),
+ * EOVERFLOW (a list longer than 2048 fragments). */
+hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                           float *rgba_out, void *stream);
+
+/* One frame: build + resolve, in several screen passes when the fragments
+ * exceed the workspace.  Same outputs and errors as the two calls above. */
+hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const hexfc_hotspot *hot,
+                                const hexfc_style *style, float *rgba_out, void *stream);
+
+/* Tuning knobs (chosen by the autotuner): screen tile of tile_w x tile_h
+ * pixels (8x8, 16x8, 16x16 or 32x8; one workgroup lane per pixel) and the
+ * longest list sorted lane-per-pixel by insertion sort (t_sort in [0, 64];
+ * longer lists use the wave-per-pixel bitonic sort).  Results do not depend
+ * on them.  Invalidates built lists. */
+hexfc_status hexfc_set_tuning(hexfc_ctx *ctx, int tile_w, int tile_h, int t_sort);
+
+/* Statistics of the last build/render (host copy, no synchronisation):
+ * out[0] bin entries, out[1] fragments, out[2] screen passes, out[8..15]
+ * pixels per length class (0: n <= t_sort; 1..6: n <= 64, 128, 256, 512,
+ * 1024, 2048; 7: longer), out[16..23] fragments per length class.
+ * n = number of entries wanted (<= 24). */
+hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n);
+
+/* Per-launch timing with HIP events recorded on the launch stream (off by
+ * default).  hexfc_get_kernel_times waits for the recorded events, returns the
+ * accumulated milliseconds and launch counts per kernel and resets them.
+ * Kernel index: 0 transform, 1 triangle binning (count + tile scan),
+ * 2 bin scatter, 3 coverage count, 4 pixel scan, 5 length classes, 6 pass
+ * plan, 7 list fill, 8 + c resolve of length class c (c = 0..6).
+ * n = number of entries wanted (<= 16). */
+hexfc_status hexfc_set_profiling(hexfc_ctx *ctx, int enable);
+hexfc_status hexfc_get_kernel_times(hexfc_ctx *ctx, double *ms_out, uint64_t *launches_out, int n);
+
+/* Total fragments of the last build/render (host value). */
+hexfc_status hexfc_get_total_fragments(hexfc_ctx *ctx, uint64_t *out);
+
+/* Parity export of the last built lists, row-major pixel order:
+ *   counts_out  device uint32 [H*W]
+ *   off_out     device uint64 [H*W + 1] exclusive offsets
+ *   rec_out     device uint64 [total fragments] records, each list sorted
+ * Errors: ESTATE (no lists). */
+hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uint64_t *off_out,
+                                       uint64_t *rec_out, void *stream);
+
+const char *hexfc_status_string(hexfc_status s);
+const char *hexfc_last_error(const hexfc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEXFC_H */

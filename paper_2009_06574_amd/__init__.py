@@ -1,0 +1,241 @@
+"""hexfc: MI355X-native focus+context hex-mesh renderer (Python binding).
+
+Thin ctypes binding of ``libhexfc.so`` (include/hexfc.h).  It only marshals
+arguments: every step of the render path runs in the library's HIP kernels.
+PyTorch provides device memory (workspace, outputs) and the current stream.
+There is no CPU fallback: if the library has not been built, ``load()``
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhexfc.so")
+
+STATUS = {0: "HEXFC_OK", -1: "HEXFC_EINVAL", -2: "HEXFC_ERANGE", -3: "HEXFC_ENOMEM",
+          -4: "HEXFC_EOVERFLOW", -5: "HEXFC_EDEVICE", -6: "HEXFC_ESTATE"}
+
+# every entry point declared in include/hexfc.h
+ABI_SYMBOLS = (
+    "hexfc_create", "hexfc_destroy", "hexfc_set_workspace", "hexfc_upload_mesh",
+    "hexfc_build_fragment_lists", "hexfc_resolve", "hexfc_render_frame", "hexfc_set_tuning",
+    "hexfc_get_frame_stats", "hexfc_get_total_fragments", "hexfc_export_sorted_lists",
+    "hexfc_set_profiling", "hexfc_get_kernel_times",
+    "hexfc_status_string", "hexfc_last_error",
+)
+
+
+class HexfcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class CCamera(ct.Structure):
+    _fields_ = [("view_proj", ct.c_float * 16), ("width", ct.c_int32), ("height", ct.c_int32)]
+
+
+class CHotspot(ct.Structure):
+    _fields_ = [("center", ct.c_float * 3), ("radius", ct.c_float)]
+
+
+class CStyle(ct.Structure):
+    _fields_ = [("w_base", ct.c_float), ("k_focus", ct.c_float), ("halo_width", ct.c_float),
+                ("halo_alpha", ct.c_float), ("darken", ct.c_float), ("accent_s", ct.c_float),
+                ("accent_brighten", ct.c_float), ("delta", ct.c_float), ("lod", ct.c_int32),
+                ("tf_rgb_lo", ct.c_float * 3), ("tf_rgb_hi", ct.c_float * 3),
+                ("tf_a_lo", ct.c_float), ("tf_a_hi", ct.c_float), ("bg", ct.c_float * 3)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhexfc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_06574_amd.build.build()")
+    lib = ct.CDLL(LIB_PATH)
+    P, i64, st = ct.c_void_p, ct.c_int64, ct.c_int
+    sig = {
+        "hexfc_create": ([ct.c_int, ct.POINTER(P)], st),
+        "hexfc_destroy": ([P], None),
+        "hexfc_set_workspace": ([P, P, ct.c_size_t], st),
+        "hexfc_upload_mesh": ([P, P, i64, P, i64, P, P], st),
+        "hexfc_build_fragment_lists": ([P, ct.POINTER(CCamera), P, P], st),
+        "hexfc_resolve": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), P, P], st),
+        "hexfc_render_frame": ([P, ct.POINTER(CCamera), ct.POINTER(CHotspot), ct.POINTER(CStyle), P, P], st),
+        "hexfc_set_tuning": ([P, ct.c_int, ct.c_int, ct.c_int], st),
+        "hexfc_get_frame_stats": ([P, P, ct.c_int], st),
+        "hexfc_get_total_fragments": ([P, P], st),
+        "hexfc_export_sorted_lists": ([P, P, P, P, P], st),
+        "hexfc_set_profiling": ([P, ct.c_int], st),
+        "hexfc_get_kernel_times": ([P, P, P, ct.c_int], st),
+        "hexfc_status_string": ([st], ct.c_char_p),
+        "hexfc_last_error": ([P], ct.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def camera_struct(cam) -> CCamera:
+    c = CCamera()
+    vp = np.asarray(cam.view_proj, dtype=np.float32).reshape(16)
+    c.view_proj[:] = [float(x) for x in vp]
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def hotspot_struct(h) -> CHotspot:
+    c = CHotspot()
+    c.center[:] = [float(x) for x in h.center]
+    c.radius = float(h.radius)
+    return c
+
+
+def style_struct(s) -> CStyle:
+    c = CStyle()
+    for k in ("w_base", "k_focus", "halo_width", "halo_alpha", "darken", "accent_s", "accent_brighten", "delta"):
+        setattr(c, k, float(getattr(s, k)))
+    c.lod = int(s.lod)
+    c.tf_rgb_lo[:] = [float(x) for x in s.tf_rgb_lo]
+    c.tf_rgb_hi[:] = [float(x) for x in s.tf_rgb_hi]
+    c.tf_a_lo, c.tf_a_hi = float(s.tf_a_lo), float(s.tf_a_hi)
+    c.bg[:] = [float(x) for x in s.bg]
+    return c
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+class Renderer:
+    """One hexfc context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        h = ct.c_void_p()
+        self._check(self.lib.hexfc_create(device, ct.byref(h)), None)
+        self.ctx = h
+        self.workspace = None
+        self.W = self.H = 0
+
+    def _check(self, status, ctx="self"):
+        if status != 0:
+            msg = ""
+            if ctx is not None and getattr(self, "ctx", None):
+                msg = (self.lib.hexfc_last_error(self.ctx) or b"").decode()
+            raise HexfcError(status, msg)
+
+    def _stream(self):
+        return ct.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hexfc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ setup
+    def set_workspace(self, nbytes: int):
+        nbytes = int(nbytes)
+        self.workspace = self.torch.empty(max(nbytes, 256), dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.hexfc_set_workspace(self.ctx, _ptr(self.workspace), nbytes))
+
+    def set_tuning(self, tile_w: int = 8, tile_h: int = 8, t_sort: int = 16):
+        self._check(self.lib.hexfc_set_tuning(self.ctx, int(tile_w), int(tile_h), int(t_sort)))
+
+    def upload_mesh(self, xyz, hexes, cell_scalar=None, cell_edge_level=None):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+        hexes = np.ascontiguousarray(hexes, dtype=np.int32)
+        sc = None if cell_scalar is None else np.ascontiguousarray(cell_scalar, dtype=np.float32)
+        lv = None if cell_edge_level is None else np.ascontiguousarray(cell_edge_level, dtype=np.uint8)
+        p = lambda a: None if a is None else a.ctypes.data_as(ct.c_void_p)
+        self._check(self.lib.hexfc_upload_mesh(self.ctx, p(xyz), xyz.shape[0], p(hexes), hexes.shape[0],
+                                               p(sc), p(lv)))
+
+    def upload(self, mesh):
+        """Upload an object with xyz / hex / cell_scalar / cell_edge_level attributes."""
+        self.upload_mesh(mesh.xyz, mesh.hex, getattr(mesh, "cell_scalar", None),
+                         getattr(mesh, "cell_edge_level", None))
+
+    # ------------------------------------------------------------ frames
+    def build(self, cam, want_counts: bool = False):
+        c = camera_struct(cam)
+        counts = None
+        if want_counts:
+            counts = self.torch.empty((c.height, c.width), dtype=self.torch.int32, device=self.device)
+        self._check(self.lib.hexfc_build_fragment_lists(self.ctx, ct.byref(c), _ptr(counts), self._stream()))
+        self.W, self.H = c.width, c.height
+        return counts
+
+    def resolve(self, hot, style, out=None):
+        if out is None:
+            out = self.torch.empty((self.H, self.W, 4), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hexfc_resolve(self.ctx, ct.byref(hotspot_struct(hot)), ct.byref(style_struct(style)),
+                                           _ptr(out), self._stream()))
+        return out
+
+    def render(self, cam, hot, style, out=None):
+        c = camera_struct(cam)
+        if out is None:
+            out = self.torch.empty((c.height, c.width, 4), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hexfc_render_frame(self.ctx, ct.byref(c), ct.byref(hotspot_struct(hot)),
+                                                ct.byref(style_struct(style)), _ptr(out), self._stream()))
+        self.W, self.H = c.width, c.height
+        return out
+
+    def export_sorted_lists(self):
+        """(counts int32 [H*W], off int64 [H*W+1], rec int64 [F]) in row-major pixel order;
+        uint32/uint64 bit patterns stored in signed tensors."""
+        n = self.W * self.H
+        F = self.total_fragments()
+        t = self.torch
+        counts = t.empty(n, dtype=t.int32, device=self.device)
+        off = t.empty(n + 1, dtype=t.int64, device=self.device)
+        rec = t.empty(max(F, 1), dtype=t.int64, device=self.device)
+        self._check(self.lib.hexfc_export_sorted_lists(self.ctx, _ptr(counts), _ptr(off), _ptr(rec), self._stream()))
+        return counts, off, rec[:F]
+
+    def total_fragments(self) -> int:
+        v = ct.c_uint64()
+        self._check(self.lib.hexfc_get_total_fragments(self.ctx, ct.byref(v)))
+        return int(v.value)
+
+    def frame_stats(self) -> dict:
+        a = (ct.c_uint64 * 24)()
+        self._check(self.lib.hexfc_get_frame_stats(self.ctx, a, 24))
+        return dict(bins=int(a[0]), fragments=int(a[1]), passes=int(a[2]),
+                    classes=[int(a[8 + i]) for i in range(8)],
+                    class_fragments=[int(a[16 + i]) for i in range(8)])
+
+    KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill") + tuple(
+        f"resolve_c{c}" for c in range(8))
+
+    def set_profiling(self, on: bool = True):
+        self._check(self.lib.hexfc_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        """Accumulated (ms, launches) per kernel since the last call (waits for the events)."""
+        ms = (ct.c_double * 16)()
+        n = (ct.c_uint64 * 16)()
+        self._check(self.lib.hexfc_get_kernel_times(self.ctx, ms, n, 16))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS) if n[i]}

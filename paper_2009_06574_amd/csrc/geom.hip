@@ -1,0 +1,547 @@
+// geom.hip -- geometry half of the per-frame path on gfx950: exact integer
+// vertex transform and snap, triangle binning to screen tiles, the coverage
+// count, the prefix scan, pass planning and the fragment-list fill.
+//
+// The paper renders every hex face as two triangles and appends one fragment
+// per covered pixel to a per-pixel list (Section 4, Section 6).  Here the
+// rasteriser is an integer edge-function test over screen tiles (one
+// workgroup per tile, one lane per pixel), and the lists are built in two
+// passes over the same bins -- count, exclusive scan, fill -- into one
+// contiguous 8-byte record per fragment, instead of atomically linked nodes.
+#include "kern.h"
+
+namespace hexfc {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ long long floordiv_pos(long long n, long long d) {  // d > 0
+    long long q = n / d;
+    long long r = n - q * d;
+    return (r < 0) ? q - 1 : q;
+}
+
+// Vertex transform (exact): clip = M_q (X_q, 2^16); screen position with 4
+// sub-pixel bits, round half up; inverse depth q = floor(2^56 / w_q).
+__global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq, int64_t V, Mat3q M,
+                                                   int W, int H, int4 *__restrict__ vscr) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int4 p = posq[v];
+    long long X = p.x, Y = p.y, Z = p.z, O = 65536;
+    long long cx = M.m[0][0] * X + M.m[0][1] * Y + M.m[0][2] * Z + M.m[0][3] * O;
+    long long cy = M.m[1][0] * X + M.m[1][1] * Y + M.m[1][2] * Z + M.m[1][3] * O;
+    long long cw = M.m[2][0] * X + M.m[2][1] * Y + M.m[2][2] * Z + M.m[2][3] * O;
+    int4 out = make_int4(0, 0, 0, 0);
+    if (cw < W_NEAR_Q) {
+        out.w = 1;
+    } else {
+        long long d = 2 * cw;
+        long long sx = floordiv_pos((cx + cw) * (long long)(W * SUB) + cw, d);
+        long long sy = floordiv_pos((cw - cy) * (long long)(H * SUB) + cw, d);
+        if (sx >= GUARD || sx <= -GUARD || sy >= GUARD || sy <= -GUARD) {
+            out.w = 2;
+        } else {
+            out.x = (int)sx;
+            out.y = (int)sy;
+            out.z = (int)(QNUM / cw);
+        }
+    }
+    vscr[v] = out;
+}
+
+// Triangle t of the face list: corners (c0,c1,c2) or (c0,c2,c3).
+__device__ __forceinline__ void tri_ids(const int4 c, int t, int &a, int &b, int &d) {
+    a = c.x;
+    b = t ? c.z : c.y;
+    d = t ? c.w : c.z;
+}
+
+// Screen-tile range of a triangle's pixel-centre bounding box; false when the
+// triangle is culled (flagged vertex, zero snapped area, nothing on screen).
+__device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+                                               int64_t tri, const Tiling &tl, int &tx0, int &tx1, int &ty0,
+                                               int &ty1) {
+    int4 c = face_v[tri >> 1];
+    int ia, ib, ic;
+    tri_ids(c, (int)(tri & 1), ia, ib, ic);
+    int4 a = vscr[ia], b = vscr[ib], d = vscr[ic];
+    if (a.w | b.w | d.w) return false;
+    long long area = (long long)(b.x - a.x) * (d.y - a.y) - (long long)(b.y - a.y) * (d.x - a.x);
+    if (area == 0) return false;
+    int xmin = min(a.x, min(b.x, d.x)), xmax = max(a.x, max(b.x, d.x));
+    int ymin = min(a.y, min(b.y, d.y)), ymax = max(a.y, max(b.y, d.y));
+    // pixel i is a candidate iff xmin <= 16 i + 8 <= xmax
+    int i0 = (int)(-floordiv_pos(-(long long)(xmin - 8), SUB));
+    int i1 = (int)floordiv_pos((long long)(xmax - 8), SUB);
+    int j0 = (int)(-floordiv_pos(-(long long)(ymin - 8), SUB));
+    int j1 = (int)floordiv_pos((long long)(ymax - 8), SUB);
+    i0 = max(i0, 0);
+    j0 = max(j0, 0);
+    i1 = min(i1, tl.W - 1);
+    j1 = min(j1, tl.H - 1);
+    if (i0 > i1 || j0 > j1) return false;
+    tx0 = i0 / tl.TW;
+    tx1 = i1 / tl.TW;
+    ty0 = j0 / tl.TH;
+    ty1 = j1 / tl.TH;
+    return true;
+}
+
+__global__ void __launch_bounds__(256) k_tri_bin_count(const int4 *__restrict__ face_v, int64_t T,
+                                                       const int4 *__restrict__ vscr, Tiling tl,
+                                                       uint32_t *__restrict__ tile_cnt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int tx0, tx1, ty0, ty1;
+    if (!tri_tile_range(face_v, vscr, t, tl, tx0, tx1, ty0, ty1)) return;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_cnt[ty * tl.ntx + tx], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_tri_bin_scatter(const int4 *__restrict__ face_v, int64_t T,
+                                                         const int4 *__restrict__ vscr, Tiling tl,
+                                                         const uint64_t *__restrict__ tile_off,
+                                                         uint32_t *__restrict__ tile_fill,
+                                                         uint32_t *__restrict__ bins, uint64_t cap) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int tx0, tx1, ty0, ty1;
+    if (!tri_tile_range(face_v, vscr, t, tl, tx0, tx1, ty0, ty1)) return;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            int tile = ty * tl.ntx + tx;
+            uint64_t idx = tile_off[tile] + atomicAdd(&tile_fill[tile], 1u);
+            if (idx < cap) bins[idx] = (uint32_t)t;
+        }
+}
+
+// ------------------------------------------------------------------ per-tile triangle setup
+
+// Coverage of one triangle over one tile, as three edge tests
+//   E'(dx, dy) = c + a*dx + b*dy >= 0
+// in int32, where (dx, dy) is the sub-pixel offset of the pixel centre from
+// the tile's first pixel centre.  The half-open rule is folded into c (-1 on
+// edges that do not own their centres).  An edge that passes everywhere on
+// the tile becomes (0,0,0); a triangle that misses the tile gets c = -1.
+struct CovSetup {
+    int a0, b0, c0, a1;
+    int b1, c1, a2, b2;
+    int c2, pad0, pad1, pad2;
+};
+// Depth key of the same triangle: N(dx, dy) = n0 + na*dx + nb*dy (exact
+// int64), key = floor(N / D) with D = twice the oriented area.
+struct KeySetup {
+    long long n0, na, nb, D;
+    double rD;
+    unsigned tri;
+    unsigned pad;
+};
+
+template <bool WITH_KEY>
+__device__ __forceinline__ void tri_setup(const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+                                          uint32_t tri, int ox, int oy, int ex, int ey, CovSetup &cs,
+                                          KeySetup &ks) {
+    int4 c = face_v[tri >> 1];
+    int ia, ib, ic;
+    tri_ids(c, (int)(tri & 1), ia, ib, ic);
+    int4 v[3] = {vscr[ia], vscr[ib], vscr[ic]};
+    cs.pad0 = cs.pad1 = cs.pad2 = 0;
+    long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
+                     (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
+    if ((v[0].w | v[1].w | v[2].w) || area == 0) {  // (culled triangles are never binned)
+        cs.a0 = cs.b0 = cs.a1 = cs.b1 = cs.a2 = cs.b2 = 0;
+        cs.c0 = -1;
+        cs.c1 = cs.c2 = 0;
+        return;
+    }
+    if (area < 0) {  // orient so the interior is on the left of every edge
+        int4 t = v[1];
+        v[1] = v[2];
+        v[2] = t;
+        area = -area;
+    }
+    int ea[3], eb[3], ec[3];
+    long long n0 = 0, na = 0, nb = 0;
+    bool reject = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int4 p = v[k], q = v[(k + 1) % 3];
+        int A = p.y - q.y, B = q.x - p.x;  // E(x,y) = A (x - px) + B (y - py)
+        long long Eo = (long long)A * (ox - p.x) + (long long)B * (oy - p.y);
+        if (WITH_KEY) {
+            long long qo = v[(k + 2) % 3].z;  // edge k is opposite vertex k+2
+            n0 += Eo * qo;
+            na += (long long)A * qo;
+            nb += (long long)B * qo;
+        }
+        bool owned = (A > 0) || (A == 0 && B > 0);  // dy < 0, or dy == 0 and dx > 0
+        long long Eb = owned ? Eo : Eo - 1;
+        long long ax = (long long)A * ex, by = (long long)B * ey;
+        long long emin = Eb + min(0LL, ax) + min(0LL, by);
+        long long emax = Eb + max(0LL, ax) + max(0LL, by);
+        if (emax < 0) reject = true;
+        if (emin >= 0) {
+            ea[k] = eb[k] = 0;
+            ec[k] = 0;
+        } else {
+            ea[k] = A;
+            eb[k] = B;
+            ec[k] = (int)Eb;
+        }
+    }
+    if (reject) {
+        cs.a0 = cs.b0 = cs.a1 = cs.b1 = cs.a2 = cs.b2 = 0;
+        cs.c0 = -1;
+        cs.c1 = cs.c2 = 0;
+    } else {
+        cs.a0 = ea[0]; cs.b0 = eb[0]; cs.c0 = ec[0];
+        cs.a1 = ea[1]; cs.b1 = eb[1]; cs.c1 = ec[1];
+        cs.a2 = ea[2]; cs.b2 = eb[2]; cs.c2 = ec[2];
+    }
+    if (WITH_KEY) {
+        ks.n0 = n0;
+        ks.na = na;
+        ks.nb = nb;
+        ks.D = area;
+        ks.rD = 1.0 / (double)area;
+        ks.tri = tri;
+        ks.pad = 0;
+    }
+}
+
+__device__ __forceinline__ bool covers(const CovSetup &s, int dx, int dy) {
+    int e0 = s.c0 + __mul24(s.a0, dx) + __mul24(s.b0, dy);
+    int e1 = s.c1 + __mul24(s.a1, dx) + __mul24(s.b1, dy);
+    int e2 = s.c2 + __mul24(s.a2, dx) + __mul24(s.b2, dy);
+    return (e0 | e1 | e2) >= 0;
+}
+
+__device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy) {
+    long long N = k.n0 + k.na * dx + k.nb * dy;
+    long long q = (long long)((double)N * k.rD);
+    long long r = N - q * k.D;
+    if (r < 0) q -= 1;
+    else if (r >= k.D) q += 1;
+    return (uint32_t)q;
+}
+
+// ------------------------------------------------------------------ count / fill
+// One workgroup of TW*TH lanes per screen tile (lane = pixel).  The tile's bin
+// is consumed in batches of NT triangles: each lane sets up one triangle into
+// LDS, then every lane tests its pixel against the whole batch.
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
+                                                  const uint32_t *__restrict__ bins,
+                                                  const int4 *__restrict__ face_v,
+                                                  const int4 *__restrict__ vscr, uint32_t *__restrict__ count,
+                                                  uint64_t cap) {
+    constexpr int NT = TW * TH;
+    __shared__ CovSetup s_cov[NT];
+    const int tile = blockIdx.x;
+    const int tx = tile % tl.ntx, ty = tile / tl.ntx;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
+    const int dx = SUB * lx, dy = SUB * ly;
+    // (bins beyond the capacity were not stored; the caller grows and redoes the frame)
+    const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
+    uint32_t n = 0;
+    KeySetup dummy;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int m = (int)min((uint64_t)NT, b1 - base);
+        if ((int)threadIdx.x < m) {
+            CovSetup cs;
+            tri_setup<false>(face_v, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
+                             dummy);
+            s_cov[threadIdx.x] = cs;
+        }
+        __syncthreads();
+        for (int j = 0; j < m; ++j) n += covers(s_cov[j], dx, dy) ? 1u : 0u;
+        __syncthreads();
+    }
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    count[(size_t)tile * NT + threadIdx.x] = (px < tl.W && py < tl.H) ? n : 0u;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int tile_lo, const uint64_t *__restrict__ tile_off,
+                                                 const uint32_t *__restrict__ bins,
+                                                 const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+                                                 const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
+                                                 uint64_t cap) {
+    constexpr int NT = TW * TH;
+    __shared__ CovSetup s_cov[NT];
+    __shared__ KeySetup s_key[NT];
+    const int tile = tile_lo + blockIdx.x;
+    const int tx = tile % tl.ntx, ty = tile / tl.ntx;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
+    const int dx = SUB * lx, dy = SUB * ly;
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool valid = px < tl.W && py < tl.H;
+    const uint64_t pass_base = off[(size_t)tile_lo * NT];
+    uint64_t *dst = rec + (off[(size_t)tile * NT + threadIdx.x] - pass_base);
+    const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
+    uint32_t n = 0;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int m = (int)min((uint64_t)NT, b1 - base);
+        if ((int)threadIdx.x < m) {
+            CovSetup cs;
+            KeySetup ks;
+            tri_setup<true>(face_v, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
+            s_cov[threadIdx.x] = cs;
+            s_key[threadIdx.x] = ks;
+        }
+        __syncthreads();
+        if (valid) {
+            for (int j = 0; j < m; ++j) {
+                if (covers(s_cov[j], dx, dy)) {
+                    const KeySetup &k = s_key[j];
+                    uint32_t key = depth_key(k, dx, dy);
+                    dst[n++] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ scan (u32 -> u64 exclusive)
+constexpr int SCAN_BS = 256, SCAN_IT = 8, SCAN_CHUNK = SCAN_BS * SCAN_IT;
+
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *sh, uint64_t &total) {
+    // Hillis-Steele over 256 threads in LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_BS; o <<= 1) {
+        uint64_t x = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[SCAN_BS - 1];
+    uint64_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                         uint64_t *__restrict__ part) {
+    __shared__ uint64_t sh[SCAN_BS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_IT;
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_IT; ++i)
+        if (base + i < n) s += in[base + i];
+    uint64_t tot;
+    block_excl_scan(s, sh, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_parts(uint64_t *__restrict__ part, int64_t nparts,
+                                                        uint64_t *__restrict__ out_total,
+                                                        uint64_t *__restrict__ stat) {
+    __shared__ uint64_t sh[SCAN_BS];
+    uint64_t carry = 0;
+    for (int64_t c = 0; c < nparts; c += SCAN_BS) {
+        int64_t i = c + threadIdx.x;
+        uint64_t v = i < nparts ? part[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_excl_scan(v, sh, tot);
+        if (i < nparts) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *out_total = carry;
+        if (stat) *stat = carry;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t *__restrict__ in, int64_t n,
+                                                        const uint64_t *__restrict__ part,
+                                                        uint64_t *__restrict__ out) {
+    __shared__ uint64_t sh[SCAN_BS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_IT;
+    uint32_t v[SCAN_IT];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_IT; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0u;
+        s += v[i];
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan(s, sh, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_IT; ++i) {
+        if (base + i < n) out[base + i] = ex;
+        ex += v[i];
+    }
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK) + 1; }
+
+void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t *tmp, uint64_t *stat,
+                         hipStream_t s) {
+    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nb > 0) k_scan_reduce<<<dim3((unsigned)nb), dim3(SCAN_BS), 0, s>>>(in, n, tmp);
+    k_scan_parts<<<1, SCAN_BS, 0, s>>>(tmp, nb, out + n, stat);
+    if (nb > 0) k_scan_apply<<<dim3((unsigned)nb), dim3(SCAN_BS), 0, s>>>(in, n, tmp, out);
+}
+
+// ------------------------------------------------------------------ pass planning
+// Greedy split of the tile sequence into passes whose fragments fit the
+// workspace (screen subdivision, Section 7).  One thread; binary search over
+// the tile prefix sums.
+__global__ void k_plan(int ntiles, int tp, const uint64_t *__restrict__ off, uint64_t budget,
+                       uint64_t *__restrict__ stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int np = 0;
+    int start = 0;
+    stats[ST_PASS] = 0;
+    stats[ST_PLAN_ERR] = 0;
+    while (start < ntiles) {
+        uint64_t s0 = off[(size_t)start * tp];
+        int lo = start, hi = ntiles;  // largest end with off[end*tp] - s0 <= budget
+        while (lo < hi) {
+            int mid = lo + (hi - lo + 1) / 2;
+            if (off[(size_t)mid * tp] - s0 <= budget) lo = mid;
+            else hi = mid - 1;
+        }
+        if (lo == start || np >= MAX_PASSES) {
+            stats[ST_PLAN_ERR] = 1;
+            break;
+        }
+        stats[ST_PASS + (++np)] = (uint64_t)lo;
+        start = lo;
+    }
+    stats[ST_NPASS] = (uint64_t)np;
+}
+
+void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, uint64_t *stats, hipStream_t s) {
+    k_plan<<<1, 64, 0, s>>>(tl.ntiles, tl.TW * tl.TH, off, budget_recs, stats);
+}
+
+// ------------------------------------------------------------------ length classes
+__device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
+    if (n <= (uint32_t)t_sort) return 0;
+    if (n <= 64) return 1;
+    if (n <= 128) return 2;
+    if (n <= 256) return 3;
+    if (n <= 512) return 4;
+    if (n <= 1024) return 5;
+    if (n <= 2048) return 6;
+    return 7;
+}
+
+__global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t p1,
+                                                  const uint32_t *__restrict__ count, int t_sort,
+                                                  uint32_t *__restrict__ lists, int64_t cap,
+                                                  uint64_t *__restrict__ stats) {
+    int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int TP = tl.TW * tl.TH;
+    int cls = -1;
+    if (p < p1) {
+        int tile = (int)(p / TP), l = (int)(p % TP);
+        int x = (tile % tl.ntx) * tl.TW + l % tl.TW;
+        int y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+        if (x < tl.W && y < tl.H) cls = length_class(count[p], t_sort);
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c = 0; c < NCLASS; ++c) {
+        unsigned long long m = __ballot(cls == c);
+        if (!m) continue;
+        unsigned long long base = 0;
+        int leader = __ffsll((long long)m) - 1;
+        if (lane == leader) base = atomicAdd((unsigned long long *)&stats[ST_CLASS + c], (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+        if (cls == c) lists[(int64_t)c * cap + base + __popcll(m & lt)] = (uint32_t)p;
+    }
+    // fragments per class (for bandwidth accounting)
+    uint64_t nf = (cls >= 0) ? (uint64_t)count[p] : 0;
+    for (int c = 0; c < NCLASS; ++c) {
+        uint64_t v = (cls == c) ? nf : 0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (lane == 0 && v) atomicAdd((unsigned long long *)&stats[ST_CLASSF + c], (unsigned long long)v);
+    }
+}
+
+void launch_classify(const Tiling &tl, int tile_lo, int tile_hi, const uint32_t *count, int t_sort,
+                     uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s) {
+    const int TP = tl.TW * tl.TH;
+    int64_t p0 = (int64_t)tile_lo * TP, p1 = (int64_t)tile_hi * TP;
+    int64_t n = p1 - p0;
+    if (n <= 0) return;
+    k_classify<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, p0, p1, count, t_sort, cls_lists, cls_cap, stats);
+}
+
+// ------------------------------------------------------------------ small utilities
+__global__ void k_zero_u64(uint64_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+void launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s) {
+    if (n > 0) k_zero_u64<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, n);
+}
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
+    if (n > 0) k_zero_u32<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, n);
+}
+
+__global__ void k_rowmajor_counts(Tiling tl, const uint32_t *__restrict__ ctm, uint32_t *__restrict__ crm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)tl.W * tl.H) return;
+    int x = (int)(i % tl.W), y = (int)(i / tl.W);
+    int tile = (y / tl.TH) * tl.ntx + x / tl.TW;
+    int l = (y % tl.TH) * tl.TW + x % tl.TW;
+    crm[i] = ctm[(int64_t)tile * tl.TW * tl.TH + l];
+}
+void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t *count_rm, hipStream_t s) {
+    int64_t n = (int64_t)tl.W * tl.H;
+    k_rowmajor_counts<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, count_tm, count_rm);
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, int4 *vscr, hipStream_t s) {
+    if (V > 0) k_transform<<<dim3((unsigned)((V + 255) / 256)), 256, 0, s>>>(posq, V, M, W, H, vscr);
+}
+void launch_tri_bin_count(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl, uint32_t *tile_cnt,
+                          hipStream_t s) {
+    if (T > 0) k_tri_bin_count<<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_v, T, vscr, tl, tile_cnt);
+}
+void launch_tri_bin_scatter(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
+                            hipStream_t s) {
+    if (T > 0)
+        k_tri_bin_scatter<<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_v, T, vscr, tl, tile_off, tile_fill,
+                                                                            bins, bin_cap);
+}
+
+#define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \
+    if (tl.TW == TWv && tl.TH == THv) { CALL; return; }
+
+void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
+                  const int4 *face_v, const int4 *vscr, uint32_t *count, hipStream_t s) {
+    dim3 g((unsigned)tl.ntiles);
+    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
+}
+
+void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off, const uint32_t *bins,
+                 uint64_t cap, const int4 *face_v, const int4 *vscr, const uint64_t *off, uint64_t *rec,
+                 hipStream_t s) {
+    if (tile_hi <= tile_lo) return;
+    dim3 g((unsigned)(tile_hi - tile_lo));
+    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
+}
+
+}  // namespace hexfc

@@ -1,0 +1,107 @@
+// kern.h -- internal declarations shared by the library's translation units
+// (device data layout, kernel launchers).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hexfc {
+
+// ---------------------------------------------------------------- constants
+constexpr int SUB = 16;                      // sub-pixels per pixel (4 bits)
+constexpr int64_t W_NEAR_Q = int64_t(1) << 32;  // w_q below this culls (w < 1/16)
+constexpr int64_t GUARD = int64_t(1) << 17;     // |s| >= GUARD culls
+constexpr int64_t QNUM = int64_t(1) << 56;      // q = floor(QNUM / w_q)
+constexpr uint32_t KMAX = 1u << 24;             // depth field = KMAX - key
+constexpr int MAX_PASSES = 64;
+constexpr int MAX_LIST = 2048;                  // longest list a resolve kernel sorts
+
+// length classes of the resolve: 0 = short (lane per pixel, n <= t_sort), then
+// wave-per-pixel bitonic sorts of 64, 128, 256, 512, 1024, 2048 padded
+// elements (classes 1..6); class 7 = longer than MAX_LIST (an error).
+constexpr int NCLASS = 8;
+
+// device-side statistics written by the kernels and read back once per frame
+enum StatSlot {
+    ST_BINS = 0,      // bin entries needed
+    ST_FRAGS = 1,     // total fragments
+    ST_NPASS = 2,     // passes planned
+    ST_PLAN_ERR = 3,  // a single tile exceeds the workspace
+    ST_CLASS = 8,     // NCLASS class sizes (pixels)
+    ST_CLASSF = 16,   // NCLASS class sizes (fragments)
+    ST_PASS = 24,     // MAX_PASSES + 1 tile boundaries
+    ST_COUNT = 24 + MAX_PASSES + 1
+};
+
+// kernels timed by the optional per-launch HIP-event profiler
+enum KernelId {
+    KID_TRANSFORM = 0, KID_BIN_COUNT, KID_BIN_SCATTER, KID_COUNT, KID_SCAN, KID_CLASSIFY, KID_PLAN, KID_FILL,
+    KID_RESOLVE0,  // + length class
+    KID_COUNT_ = KID_RESOLVE0 + NCLASS
+};
+
+struct Mat3q { long long m[3][4]; };  // rows x, y, w of M_q
+
+// Mesh arrays resident on the device.
+struct DevMesh {
+    const int4 *posq;       // [V] (X_q, Y_q, Z_q, 0)
+    const float4 *vpt;      // [V] (x, y, z, t_v) dequantised world position + importance
+    const int4 *face_v;     // [F] corner ids c0..c3
+    const uint32_t *face_lvl;  // [F] 4 x u8 edge levels, edge k = (c_k, c_{k+1})
+    const float4 *face_te;  // [F] edge importance
+    int64_t V, F;
+};
+
+struct ShadeParams {
+    float hc[3], inv_r;
+    float w_base, k_focus, halo_w, halo_a, darken, s, bright, delta;
+    int lod;
+    float lo[3], hi[3], a_lo, a_hi, bg[3];
+};
+
+struct Tiling {
+    int W, H, TW, TH, ntx, nty, ntiles;
+};
+
+// ---------------------------------------------------------------- launchers (geom.hip)
+void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, int4 *vscr, hipStream_t s);
+void launch_tri_bin_count(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+                          uint32_t *tile_cnt, hipStream_t s);
+void launch_tri_bin_scatter(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins,
+                            uint64_t bin_cap, hipStream_t s);
+void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
+                  const int4 *face_v, const int4 *vscr, uint32_t *count, hipStream_t s);
+void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off,
+                 const uint32_t *bins, uint64_t cap, const int4 *face_v, const int4 *vscr,
+                 const uint64_t *off, uint64_t *rec, hipStream_t s);
+// exclusive scan of n uint32 values into n+1 uint64 values (out[n] = total);
+// `stat` (nullable) receives the total.  tmp: scan_tmp_elems(n) uint64s.
+size_t scan_tmp_elems(int64_t n);
+void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t *tmp,
+                         uint64_t *stat, hipStream_t s);
+void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, uint64_t *stats,
+                 hipStream_t s);
+void launch_classify(const Tiling &tl, int tile_lo, int tile_hi, const uint32_t *count,
+                     int t_sort, uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s);
+void launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t *count_rm, hipStream_t s);
+
+// ---------------------------------------------------------------- launchers (resolve.hip)
+struct ResolveArgs {
+    Tiling tl;
+    DevMesh mesh;
+    const int4 *vscr;
+    const uint32_t *count;   // tile-major
+    const uint64_t *off;     // tile-major
+    const uint64_t *rec;     // workspace (pass-relative)
+    int64_t pass_p0;         // first pixel (tile-major) of the pass; records are relative to off[pass_p0]
+    ShadeParams sp;
+    float *rgba;             // row-major, nullable (sort-only)
+    uint64_t *sorted_out;    // nullable: sorted records, row-major CSR
+    const uint64_t *off_rm;  // row-major offsets for sorted_out
+};
+void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, int t_sort,
+                          const ResolveArgs &a, hipStream_t s);
+
+}  // namespace hexfc

@@ -1,0 +1,291 @@
+// resolve.hip -- per-pixel sort, focus+context shading and front-to-back
+// compositing on gfx950.
+//
+// The paper sorts each per-pixel list by distance to the camera with a GPU
+// priority queue and alpha-blends the fragments in that order (Section 3,
+// Section 6); each fragment's colour comes from Eq. 1-4 (Section 4).  Here the
+// shading is deferred until after the sort (lists then do not depend on lens
+// or style), and lists are sorted by length class:
+//   * short lists (n <= t_sort): one lane per pixel, insertion sort in an LDS
+//     column private to the lane, then a sequential front-to-back blend;
+//   * long lists: one wave per pixel, bitonic sort of 64*R keys held R per
+//     lane in registers (cross-lane stages by lane shuffles), every lane
+//     shading its R fragments in parallel, then an ordered wave reduction
+//     with the associative "over" operator.
+#include "kern.h"
+
+namespace hexfc {
+
+// Sort key order: record = (depth field << 32) | triangle id, ascending.
+
+struct Frag {
+    float r, g, b, a;
+};
+
+__device__ __forceinline__ float segdist(float px, float py, float pz, float ax, float ay, float az, float bx, float by,
+                                         float bz) {
+    float ux = bx - ax, uy = by - ay, uz = bz - az;
+    float wx = px - ax, wy = py - ay, wz = pz - az;
+    float l2 = ux * ux + uy * uy + uz * uz;
+    float t = l2 > 0.f ? (wx * ux + wy * uy + wz * uz) / l2 : 0.f;
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    float dx = wx - t * ux, dy = wy - t * uy, dz = wz - t * uz;
+    return sqrtf(dx * dx + dy * dy + dz * dz);
+}
+
+// Premultiplied colour and opacity of one fragment: triangle `tri` at pixel
+// (x, y).  Eq. 1 (edges, with the focus-edge halo and darkening), Eq. 2
+// (accentuation), Eq. 3 (face opacity), Eq. 4 (edge/face blend).
+__device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x, int y) {
+    const DevMesh &m = a.mesh;
+    const ShadeParams &sp = a.sp;
+    const uint32_t f = tri >> 1;
+    const bool t1 = tri & 1;
+    const int4 c = m.face_v[f];
+    const int ib = t1 ? c.z : c.y, ic = t1 ? c.w : c.z;
+    const int4 s0 = a.vscr[c.x], s1 = a.vscr[ib], s2 = a.vscr[ic];
+    // perspective-correct barycentrics: weight of vertex i = E_opp(i) * q_i,
+    // the edge functions being exact in FP64
+    const double X = (double)(SUB * x + SUB / 2), Y = (double)(SUB * y + SUB / 2);
+    const double e0 = (double)(s2.x - s1.x) * (Y - s1.y) - (double)(s2.y - s1.y) * (X - s1.x);
+    const double e1 = (double)(s0.x - s2.x) * (Y - s2.y) - (double)(s0.y - s2.y) * (X - s2.x);
+    const double e2 = (double)(s1.x - s0.x) * (Y - s0.y) - (double)(s1.y - s0.y) * (X - s0.x);
+    const double w0 = e0 * (double)s0.z, w1 = e1 * (double)s1.z, w2 = e2 * (double)s2.z;
+    const float inv = 1.0f / (float)(w0 + w1 + w2);
+    const float l0 = (float)w0 * inv, l1 = (float)w1 * inv, l2 = (float)w2 * inv;
+    // corners relative to corner 0 (exact: all are multiples of 2^-16)
+    const float4 P0 = m.vpt[c.x], P1 = m.vpt[c.y], P2 = m.vpt[c.z], P3 = m.vpt[c.w];
+    const float r1x = P1.x - P0.x, r1y = P1.y - P0.y, r1z = P1.z - P0.z;
+    const float r2x = P2.x - P0.x, r2y = P2.y - P0.y, r2z = P2.z - P0.z;
+    const float r3x = P3.x - P0.x, r3y = P3.y - P0.y, r3z = P3.z - P0.z;
+    const float bx = t1 ? r2x : r1x, by = t1 ? r2y : r1y, bz = t1 ? r2z : r1z;
+    const float cx = t1 ? r3x : r2x, cy = t1 ? r3y : r2y, cz = t1 ? r3z : r2z;
+    const float px = l1 * bx + l2 * cx, py = l1 * by + l2 * cy, pz = l1 * bz + l2 * cz;
+    const float tb = t1 ? P2.w : P1.w, tc = t1 ? P3.w : P2.w;
+    const float tf = l0 * P0.w + l1 * tb + l2 * tc;
+    // focus (object-space sphere)
+    const float hx = (P0.x - sp.hc[0]) + px, hy = (P0.y - sp.hc[1]) + py, hz = (P0.z - sp.hc[2]) + pz;
+    const float dist = sqrtf(hx * hx + hy * hy + hz * hz) * sp.inv_r;
+    float u = fminf(fmaxf((dist - 0.7f) * (1.0f / 0.3f), 0.f), 1.f);
+    const float focus = 1.f - u * u * (3.f - 2.f * u);
+    // distances to the four face edges
+    float d[4];
+    d[0] = segdist(px, py, pz, 0.f, 0.f, 0.f, r1x, r1y, r1z);
+    d[1] = segdist(px, py, pz, r1x, r1y, r1z, r2x, r2y, r2z);
+    d[2] = segdist(px, py, pz, r2x, r2y, r2z, r3x, r3y, r3z);
+    d[3] = segdist(px, py, pz, r3x, r3y, r3z, 0.f, 0.f, 0.f);
+    const uint32_t lv = m.face_lvl[f];
+    const float4 te4 = m.face_te[f];
+    const float te[4] = {te4.x, te4.y, te4.z, te4.w};
+    // nearest visible edge of each set (ties: lower local edge index)
+    float dF = INFINITY, dC = INFINITY, dA = d[0], tF = 0.f, tC = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool inC = (int)((lv >> (8 * k)) & 0xffu) >= sp.lod;
+        const bool inF = inC || te[k] >= sp.delta;
+        if (inF && d[k] < dF) { dF = d[k]; tF = te[k]; }
+        if (inC && d[k] < dC) { dC = d[k]; tC = te[k]; }
+        dA = fminf(dA, d[k]);
+    }
+    const float w = (1.f + sp.k_focus * focus) * sp.w_base;
+    const bool eF = dF <= w, eC = dC <= w;
+    const bool h = !eF && dF <= w + sp.halo_w * focus;
+    const float dk = 1.f - sp.darken * focus;
+    const float AF = eF ? 1.f : (h ? sp.halo_a : 0.f);
+    const float fe = eC ? 1.f - focus : 0.f;  // (1 - focus) * e_C
+    float Ce[3];
+    Frag o;
+    const float ae = fe + focus * AF;
+    const bool acc = dA <= (2.f / 3.f) * sp.w_base;
+    const float se = acc ? sp.s : 1.f;
+    const float ahat = sp.a_lo + (sp.a_hi - sp.a_lo) * tf;
+    const float dc = fminf(dist, 1.f);
+    const float dc2 = dc * dc;
+    const float afs = fminf(se * (ahat * dc2 * dc2), 1.f);
+    const float gain = (se != 1.f) ? 1.f + sp.bright : 1.f;
+    const float wf = (1.f - ae) * afs;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float lo = sp.lo[ch], span = sp.hi[ch] - sp.lo[ch];
+        const float PF = eF ? (lo + span * tF) * dk : (h ? sp.halo_a : 0.f);
+        const float cf = fminf((lo + span * tf) * gain, se != 1.f ? 1.f : INFINITY);
+        Ce[ch] = fe * (lo + span * tC) + focus * PF + wf * cf;
+    }
+    o.r = Ce[0];
+    o.g = Ce[1];
+    o.b = Ce[2];
+    o.a = ae + wf;
+    return o;
+}
+
+__device__ __forceinline__ void pixel_xy(const Tiling &tl, uint32_t p, int &x, int &y) {
+    const int TP = tl.TW * tl.TH;
+    const int tile = (int)(p / TP), l = (int)(p % TP);
+    x = (tile % tl.ntx) * tl.TW + l % tl.TW;
+    y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+}
+
+constexpr float T_EPS = 9.5367431640625e-07f;  // 2^-20: stop once 1 - A is below it
+
+// ------------------------------------------------------------------ short lists
+template <int TS>
+__global__ void __launch_bounds__(64) k_resolve_short(const uint32_t *__restrict__ list, uint32_t npix,
+                                                      ResolveArgs a) {
+    __shared__ uint64_t col[TS][64];
+    const int lane = threadIdx.x;
+    const uint32_t idx = blockIdx.x * 64 + lane;
+    if (idx >= npix) return;
+    const uint32_t p = list[idx];
+    const uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
+    const uint64_t *src = a.rec + (a.off[p] - a.off[a.pass_p0]);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t r = src[i];
+        int j = (int)i;
+        while (j > 0 && col[j - 1][lane] > r) {
+            col[j][lane] = col[j - 1][lane];
+            --j;
+        }
+        col[j][lane] = r;
+    }
+    int x, y;
+    pixel_xy(a.tl, p, x, y);
+    if (a.sorted_out) {
+        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)y * a.tl.W + x];
+        for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
+    }
+    if (a.rgba) {
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+        for (uint32_t i = 0; i < n; ++i) {
+            const float T = 1.f - A;
+            if (T < T_EPS) break;
+            const Frag fr = shade(a, (uint32_t)(col[i][lane] & 0xffffffffu), x, y);
+            C0 += T * fr.r;
+            C1 += T * fr.g;
+            C2 += T * fr.b;
+            A += T * fr.a;
+        }
+        const float T = 1.f - A;
+        float4 out = make_float4(C0 + T * a.sp.bg[0], C1 + T * a.sp.bg[1], C2 + T * a.sp.bg[2], A);
+        reinterpret_cast<float4 *>(a.rgba)[(int64_t)y * a.tl.W + x] = out;
+    }
+}
+
+// ------------------------------------------------------------------ long lists
+// Element e = lane*R + r of the padded list lives in register v[r] of `lane`.
+template <int R>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&v)[R], int lane) {
+    constexpr int N = 64 * R;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= R) {
+                const int lm = j / R;
+                const bool lower = (lane & lm) == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint64_t o = __shfl_xor(v[r], lm);
+                    const bool up = ((lane * R + r) & k) == 0;
+                    v[r] = (lower == up) ? (v[r] < o ? v[r] : o) : (v[r] < o ? o : v[r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((r & j) == 0) {
+                        const int r2 = r | j;
+                        const bool up = ((lane * R + r) & k) == 0;
+                        const uint64_t x = v[r], y = v[r2];
+                        const bool sw = up ? (x > y) : (x < y);
+                        v[r] = sw ? y : x;
+                        v[r2] = sw ? x : y;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_resolve_long(const uint32_t *__restrict__ list, uint32_t npix,
+                                                      ResolveArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= npix) return;
+    const uint32_t p = list[wave];
+    const uint32_t n = a.count[p];
+    const uint64_t *src = a.rec + (a.off[p] - a.off[a.pass_p0]);
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        v[r] = e < n ? src[e] : ~0ull;
+    }
+    bitonic_sort<R>(v, lane);
+    int x, y;
+    pixel_xy(a.tl, p, x, y);
+    if (a.sorted_out) {
+        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)y * a.tl.W + x];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = lane * R + r;
+            if (e < n) dst[e] = v[r];
+        }
+    }
+    if (a.rgba) {
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = lane * R + r;
+            if (e < n) {
+                const Frag fr = shade(a, (uint32_t)(v[r] & 0xffffffffu), x, y);
+                const float T = 1.f - A;
+                C0 += T * fr.r;
+                C1 += T * fr.g;
+                C2 += T * fr.b;
+                A += T * fr.a;
+            }
+        }
+        // ordered reduction: lane l's run precedes lane l+1's
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o),
+                        qa = __shfl_down(A, o);
+            if ((lane & (2 * o - 1)) == 0) {
+                const float T = 1.f - A;
+                C0 += T * q0;
+                C1 += T * q1;
+                C2 += T * q2;
+                A += T * qa;
+            }
+        }
+        if (lane == 0) {
+            const float T = 1.f - A;
+            float4 out = make_float4(C0 + T * a.sp.bg[0], C1 + T * a.sp.bg[1], C2 + T * a.sp.bg[2], A);
+            reinterpret_cast<float4 *>(a.rgba)[(int64_t)y * a.tl.W + x] = out;
+        }
+    }
+}
+
+void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, int t_sort, const ResolveArgs &a,
+                          hipStream_t s) {
+    if (npix == 0) return;
+    if (cls == 0) {
+        dim3 g((npix + 63) / 64);
+        if (t_sort <= 16) k_resolve_short<16><<<g, 64, 0, s>>>(pix_list, npix, a);
+        else if (t_sort <= 32) k_resolve_short<32><<<g, 64, 0, s>>>(pix_list, npix, a);
+        else k_resolve_short<64><<<g, 64, 0, s>>>(pix_list, npix, a);
+        return;
+    }
+    dim3 g((npix + 3) / 4);
+    switch (cls) {
+        case 1: k_resolve_long<1><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 2: k_resolve_long<2><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 3: k_resolve_long<4><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 4: k_resolve_long<8><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 5: k_resolve_long<16><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 6: k_resolve_long<32><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        default: break;
+    }
+}
+
+}  // namespace hexfc
