@@ -623,7 +623,11 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
                                 const hexfc_style *style, float *rgba_out, void *stream) {
     if (!ctx) return HEXFC_EINVAL;
     if (!ctx->ws) FAIL(ctx, HEXFC_ESTATE, "no workspace set");
-    hexfc_status st = check_shading(ctx, hot, style, rgba_out);
+    if (ctx->V == 0) FAIL(ctx, HEXFC_ESTATE, "no mesh uploaded");
+    Mat3q M;
+    hexfc_status st = check_camera(ctx, cam, M);  // camera limits first (ERANGE)
+    if (st) return st;
+    st = check_shading(ctx, hot, style, rgba_out);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     ctx->lists_valid = false;
