@@ -54,11 +54,24 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-row-step", type=int, default=8)
     ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 4 plain device copies of MIB MiB (scale for HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the screen-space split across GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 4, "read_kib": n / 1024, "write_kib": n / 1024}))
+        return
 
     import numpy as np
     import torch

@@ -50,14 +50,14 @@ struct hexfc_ctx {
     std::string err;
     // mesh
     int64_t V = 0, C = 0, F = 0;
-    DevBuf posq, vpt, face_v, face_lvl, face_te;
+    DevBuf posq, vert, face, face_c, vscr;
     // tuning
     int tw = 8, th = 8, t_sort = 16;
     // workspace (caller-owned)
     uint64_t *ws = nullptr;
     size_t ws_bytes = 0;
     // per-frame scratch
-    DevBuf vscr, tile_cnt, tile_fill, tile_off, bins, count, off, scan_tmp, cls, stats;
+    DevBuf tile_cnt, tile_fill, tile_off, bins, masks, count, off, scan_tmp, cls, stats;
     DevBuf count_rm_tmp;
     uint64_t bin_cap = 0;
     int64_t cls_cap = 0;
@@ -169,7 +169,7 @@ struct EdgeRec {
     float t;
     uint8_t lvl;
 };
-struct FaceRec {
+struct FaceKey {
     uint64_t hi, lo;  // sorted corner ids
     int64_t idx;      // 6*cell + local face
 };
@@ -317,18 +317,18 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
         ed.swap(u);
     }
     // unique faces, first-seen order
-    std::vector<FaceRec> fr((size_t)(6 * C));
+    std::vector<FaceKey> fr((size_t)(6 * C));
     for (int64_t c = 0; c < C; ++c)
         for (int f = 0; f < 6; ++f) {
             uint32_t k[4];
             for (int i = 0; i < 4; ++i) k[i] = (uint32_t)hex[8 * c + kFace[f][i]];
             std::sort(k, k + 4);
-            FaceRec &r = fr[6 * c + f];
+            FaceKey &r = fr[6 * c + f];
             r.hi = ((uint64_t)k[0] << 32) | k[1];
             r.lo = ((uint64_t)k[2] << 32) | k[3];
             r.idx = 6 * c + f;
         }
-    std::sort(fr.begin(), fr.end(), [](const FaceRec &x, const FaceRec &y) {
+    std::sort(fr.begin(), fr.end(), [](const FaceKey &x, const FaceKey &y) {
         if (x.hi != y.hi) return x.hi < y.hi;
         if (x.lo != y.lo) return x.lo < y.lo;
         return x.idx < y.idx;
@@ -340,47 +340,51 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
     std::sort(first.begin(), first.end());
     const int64_t F = (int64_t)first.size();
     if (2 * F >= (int64_t(1) << 31)) FAIL(ctx, HEXFC_ERANGE, "too many faces");
-    std::vector<int32_t> fv(4 * F);
-    std::vector<uint32_t> flv(F);
-    std::vector<float> fte(4 * F);
+    std::vector<FaceRec> frec(std::max<int64_t>(F, 1));
     for (int64_t f = 0; f < F; ++f) {
         int64_t c = first[f] / 6, lf = first[f] % 6;
-        for (int i = 0; i < 4; ++i) fv[4 * f + i] = hex[8 * c + kFace[lf][i]];
+        int32_t cv[4];
+        for (int i = 0; i < 4; ++i) cv[i] = hex[8 * c + kFace[lf][i]];
+        FaceRec &r = frec[f];
+        r.c = make_int4(cv[0], cv[1], cv[2], cv[3]);
+        float te[4];
         uint32_t lv = 0;
         for (int k = 0; k < 4; ++k) {
-            uint32_t a = (uint32_t)fv[4 * f + k], b = (uint32_t)fv[4 * f + (k + 1) % 4];
+            uint32_t a = (uint32_t)cv[k], b = (uint32_t)cv[(k + 1) % 4];
             uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
-            auto it = std::lower_bound(ed.begin(), ed.end(), key, [](const EdgeRec &r, uint64_t kk) { return r.key < kk; });
+            auto it = std::lower_bound(ed.begin(), ed.end(), key, [](const EdgeRec &e, uint64_t kk) { return e.key < kk; });
             lv |= (uint32_t)it->lvl << (8 * k);
-            fte[4 * f + k] = it->t;
+            te[k] = it->t;
         }
-        flv[f] = lv;
+        r.te = make_float4(te[0], te[1], te[2], te[3]);
+        r.lvl = lv;
+        r.pad0 = r.pad1 = r.pad2 = 0;
     }
     // device arrays
     std::vector<int32_t> posq4(4 * V);
-    std::vector<float> vpt(4 * V);
+    std::vector<VertRec> vrec(V);
     for (int64_t v = 0; v < V; ++v) {
-        for (int a = 0; a < 3; ++a) {
-            posq4[4 * v + a] = q[3 * v + a];
-            vpt[4 * v + a] = (float)(q[3 * v + a] / 65536.0);
-        }
+        for (int a = 0; a < 3; ++a) posq4[4 * v + a] = q[3 * v + a];
         posq4[4 * v + 3] = 0;
-        vpt[4 * v + 3] = (float)tv[v];
+        vrec[v].world = make_float4((float)(q[3 * v] / 65536.0), (float)(q[3 * v + 1] / 65536.0),
+                                    (float)(q[3 * v + 2] / 65536.0), (float)tv[v]);
+        vrec[v].scr = make_int4(0, 0, 0, 1);
     }
     hexfc_status st = set_device(ctx);
     if (st) return st;
     HIPCHK(ctx, hipDeviceSynchronize());
     HIPCHK(ctx, ctx->posq.ensure(sizeof(int32_t) * 4 * V));
-    HIPCHK(ctx, ctx->vpt.ensure(sizeof(float) * 4 * V));
-    HIPCHK(ctx, ctx->face_v.ensure(sizeof(int32_t) * 4 * std::max<int64_t>(F, 1)));
-    HIPCHK(ctx, ctx->face_lvl.ensure(sizeof(uint32_t) * std::max<int64_t>(F, 1)));
-    HIPCHK(ctx, ctx->face_te.ensure(sizeof(float) * 4 * std::max<int64_t>(F, 1)));
+    HIPCHK(ctx, ctx->vert.ensure(sizeof(VertRec) * V));
+    HIPCHK(ctx, ctx->face.ensure(sizeof(FaceRec) * std::max<int64_t>(F, 1)));
     HIPCHK(ctx, hipMemcpy(ctx->posq.p, posq4.data(), sizeof(int32_t) * 4 * V, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(ctx->vpt.p, vpt.data(), sizeof(float) * 4 * V, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(ctx->vert.p, vrec.data(), sizeof(VertRec) * V, hipMemcpyHostToDevice));
+    HIPCHK(ctx, ctx->face_c.ensure(sizeof(int4) * std::max<int64_t>(F, 1)));
+    HIPCHK(ctx, ctx->vscr.ensure(sizeof(int4) * V));
     if (F) {
-        HIPCHK(ctx, hipMemcpy(ctx->face_v.p, fv.data(), sizeof(int32_t) * 4 * F, hipMemcpyHostToDevice));
-        HIPCHK(ctx, hipMemcpy(ctx->face_lvl.p, flv.data(), sizeof(uint32_t) * F, hipMemcpyHostToDevice));
-        HIPCHK(ctx, hipMemcpy(ctx->face_te.p, fte.data(), sizeof(float) * 4 * F, hipMemcpyHostToDevice));
+        std::vector<int4> fc(F);
+        for (int64_t f = 0; f < F; ++f) fc[f] = frec[f].c;
+        HIPCHK(ctx, hipMemcpy(ctx->face.p, frec.data(), sizeof(FaceRec) * F, hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(ctx->face_c.p, fc.data(), sizeof(int4) * F, hipMemcpyHostToDevice));
     }
     ctx->V = V;
     ctx->C = C;
@@ -412,10 +416,10 @@ hexfc_status check_camera(hexfc_ctx *ctx, const hexfc_camera *cam, Mat3q &M) {
 DevMesh dev_mesh(const hexfc_ctx *ctx) {
     DevMesh m;
     m.posq = ctx->posq.as<int4>();
-    m.vpt = ctx->vpt.as<float4>();
-    m.face_v = ctx->face_v.as<int4>();
-    m.face_lvl = ctx->face_lvl.as<uint32_t>();
-    m.face_te = ctx->face_te.as<float4>();
+    m.vert = ctx->vert.as<VertRec>();
+    m.face = ctx->face.as<FaceRec>();
+    m.face_c = ctx->face_c.as<int4>();
+    m.vscr = ctx->vscr.as<int4>();
     m.V = ctx->V;
     m.F = ctx->F;
     return m;
@@ -447,7 +451,6 @@ hexfc_status prepare_frame(hexfc_ctx *ctx, const hexfc_camera *cam, hipStream_t 
     const int64_t TP = (int64_t)tl.TW * tl.TH;
     const int64_t np = (int64_t)tl.ntiles * TP;
     const int64_t T = 2 * ctx->F;
-    HIPCHK(ctx, ctx->vscr.ensure(sizeof(int4) * ctx->V));
     HIPCHK(ctx, ctx->tile_cnt.ensure(sizeof(uint32_t) * tl.ntiles));
     HIPCHK(ctx, ctx->tile_fill.ensure(sizeof(uint32_t) * tl.ntiles));
     HIPCHK(ctx, ctx->tile_off.ensure(sizeof(uint64_t) * (tl.ntiles + 1)));
@@ -458,18 +461,20 @@ hexfc_status prepare_frame(hexfc_ctx *ctx, const hexfc_camera *cam, hipStream_t 
         HIPCHK(ctx, ctx->cls.ensure(sizeof(uint32_t) * NCLASS * np));
         ctx->cls_cap = np;
     }
+    const int nw = (int)(TP / 64);
     if (ctx->bin_cap == 0) {
         uint64_t cap = (uint64_t)(2 * T + 65536);
         HIPCHK(ctx, ctx->bins.ensure(sizeof(uint32_t) * cap));
         ctx->bin_cap = cap;
     }
+    HIPCHK(ctx, ctx->masks.ensure(sizeof(uint64_t) * ctx->bin_cap * nw));
     uint64_t *stats = ctx->stats.as<uint64_t>();
     const uint64_t budget = ctx->ws ? ctx->ws_bytes / 8 : 0;
-    const int4 *fv = ctx->face_v.as<int4>();
+    const int4 *fv = ctx->face_c.as<int4>();
     int4 *vscr = ctx->vscr.as<int4>();
     {
         ScopedTimer tm(ctx, s, KID_TRANSFORM);
-        launch_transform(ctx->posq.as<int4>(), ctx->V, M, tl.W, tl.H, vscr, s);
+        launch_transform(ctx->posq.as<int4>(), ctx->V, M, tl.W, tl.H, ctx->vert.as<VertRec>(), vscr, s);
     }
     launch_zero_u64(stats, ST_COUNT, s);
     launch_zero_u32(ctx->tile_cnt.as<uint32_t>(), tl.ntiles, s);
@@ -490,7 +495,7 @@ hexfc_status prepare_frame(hexfc_ctx *ctx, const hexfc_camera *cam, hipStream_t 
         {
             ScopedTimer tm(ctx, s, KID_COUNT);
             launch_count(tl, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, fv, vscr,
-                         ctx->count.as<uint32_t>(), s);
+                         ctx->count.as<uint32_t>(), ctx->masks.as<uint64_t>(), s);
         }
         {
             ScopedTimer tm(ctx, s, KID_SCAN);
@@ -513,6 +518,7 @@ hexfc_status prepare_frame(hexfc_ctx *ctx, const hexfc_camera *cam, hipStream_t 
         uint64_t cap = need + need / 4 + 65536;
         HIPCHK(ctx, hipStreamSynchronize(s));
         HIPCHK(ctx, ctx->bins.ensure(sizeof(uint32_t) * cap));
+        HIPCHK(ctx, ctx->masks.ensure(sizeof(uint64_t) * cap * nw));
         ctx->bin_cap = cap;
     }
     ctx->tl = tl;
@@ -525,7 +531,6 @@ ResolveArgs resolve_args(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_s
     ResolveArgs a;
     a.tl = ctx->tl;
     a.mesh = dev_mesh(ctx);
-    a.vscr = ctx->vscr.as<int4>();
     a.count = ctx->count.as<uint32_t>();
     a.off = ctx->off.as<uint64_t>();
     a.rec = ctx->ws;
@@ -577,7 +582,8 @@ void launch_classes(hexfc_ctx *ctx, const ResolveArgs &a, const uint64_t *cls_co
 void timed_fill(hexfc_ctx *ctx, int t0, int t1, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_FILL);
     launch_fill(ctx->tl, t0, t1, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
-                ctx->face_v.as<int4>(), ctx->vscr.as<int4>(), ctx->off.as<uint64_t>(), ctx->ws, s);
+                ctx->face_c.as<int4>(), ctx->vscr.as<int4>(), ctx->off.as<uint64_t>(), ctx->ws,
+                ctx->masks.as<uint64_t>(), s);
 }
 
 }  // namespace

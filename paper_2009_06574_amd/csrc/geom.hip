@@ -23,7 +23,8 @@ __device__ __forceinline__ long long floordiv_pos(long long n, long long d) {  /
 // Vertex transform (exact): clip = M_q (X_q, 2^16); screen position with 4
 // sub-pixel bits, round half up; inverse depth q = floor(2^56 / w_q).
 __global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq, int64_t V, Mat3q M,
-                                                   int W, int H, int4 *__restrict__ vscr) {
+                                                   int W, int H, VertRec *__restrict__ vert,
+                                                   int4 *__restrict__ vscr) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     int4 p = posq[v];
@@ -46,7 +47,8 @@ __global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq
             out.z = (int)(QNUM / cw);
         }
     }
-    vscr[v] = out;
+    vert[v].scr = out;  // for shading
+    vscr[v] = out;      // dense copy for the rasteriser
 }
 
 // Triangle t of the face list: corners (c0,c1,c2) or (c0,c2,c3).
@@ -58,10 +60,10 @@ __device__ __forceinline__ void tri_ids(const int4 c, int t, int &a, int &b, int
 
 // Screen-tile range of a triangle's pixel-centre bounding box; false when the
 // triangle is culled (flagged vertex, zero snapped area, nothing on screen).
-__device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+__device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
                                                int64_t tri, const Tiling &tl, int &tx0, int &tx1, int &ty0,
                                                int &ty1) {
-    int4 c = face_v[tri >> 1];
+    int4 c = face_c[tri >> 1];
     int ia, ib, ic;
     tri_ids(c, (int)(tri & 1), ia, ib, ic);
     int4 a = vscr[ia], b = vscr[ib], d = vscr[ic];
@@ -87,32 +89,40 @@ __device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_v, 
     return true;
 }
 
-__global__ void __launch_bounds__(256) k_tri_bin_count(const int4 *__restrict__ face_v, int64_t T,
-                                                       const int4 *__restrict__ vscr, Tiling tl,
-                                                       uint32_t *__restrict__ tile_cnt) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int tx0, tx1, ty0, ty1;
-    if (!tri_tile_range(face_v, vscr, t, tl, tx0, tx1, ty0, ty1)) return;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_cnt[ty * tl.ntx + tx], 1u);
-}
-
-__global__ void __launch_bounds__(256) k_tri_bin_scatter(const int4 *__restrict__ face_v, int64_t T,
-                                                         const int4 *__restrict__ vscr, Tiling tl,
-                                                         const uint64_t *__restrict__ tile_off,
-                                                         uint32_t *__restrict__ tile_fill,
-                                                         uint32_t *__restrict__ bins, uint64_t cap) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int tx0, tx1, ty0, ty1;
-    if (!tri_tile_range(face_v, vscr, t, tl, tx0, tx1, ty0, ty1)) return;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            int tile = ty * tl.ntx + tx;
-            uint64_t idx = tile_off[tile] + atomicAdd(&tile_fill[tile], 1u);
-            if (idx < cap) bins[idx] = (uint32_t)t;
+// Triangle binning.  Each triangle adds itself to every screen tile its
+// pixel-centre bounding box overlaps.  Consecutive faces are mesh
+// neighbours, so the 64 triangles of a wave hit few distinct tiles: the lanes
+// that hit the same tile are merged into one atomic (leader election by
+// ballot), and each gets its rank inside the merged group.
+template <bool SCATTER>
+__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t T,
+                                                 const int4 *__restrict__ vscr, Tiling tl,
+                                                 uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
+                                                 uint32_t *__restrict__ bins, uint64_t cap) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+    const bool ok = t < T && tri_tile_range(face_c, vscr, t, tl, tx0, tx1, ty0, ty1);
+    const int nx = ok ? tx1 - tx0 + 1 : 1;
+    const int n = ok ? nx * (ty1 - ty0 + 1) : 0;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int k = 0; __any(k < n); ++k) {
+        const int tile = (k < n) ? (ty0 + k / nx) * tl.ntx + tx0 + k % nx : -1;
+        unsigned long long pend = __ballot(tile >= 0);
+        while (pend) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const int lead_tile = __shfl(tile, leader);
+            const unsigned long long same = __ballot(tile == lead_tile);
+            unsigned base = 0;
+            if (lane == leader) base = atomicAdd(&tile_ctr[lead_tile], (unsigned)__popcll(same));
+            base = __shfl(base, leader);
+            if (SCATTER && tile == lead_tile) {
+                const uint64_t idx = tile_off[lead_tile] + base + (uint64_t)__popcll(same & below);
+                if (idx < cap) bins[idx] = (uint32_t)t;
+            }
+            pend &= ~same;
         }
+    }
 }
 
 // ------------------------------------------------------------------ per-tile triangle setup
@@ -138,10 +148,10 @@ struct KeySetup {
 };
 
 template <bool WITH_KEY>
-__device__ __forceinline__ void tri_setup(const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+__device__ __forceinline__ void tri_setup(const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
                                           uint32_t tri, int ox, int oy, int ex, int ey, CovSetup &cs,
                                           KeySetup &ks) {
-    int4 c = face_v[tri >> 1];
+    int4 c = face_c[tri >> 1];
     int ia, ib, ic;
     tri_ids(c, (int)(tri & 1), ia, ib, ic);
     int4 v[3] = {vscr[ia], vscr[ib], vscr[ic]};
@@ -228,21 +238,26 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 // ------------------------------------------------------------------ count / fill
 // One workgroup of TW*TH lanes per screen tile (lane = pixel).  The tile's bin
 // is consumed in batches of NT triangles: each lane sets up one triangle into
-// LDS, then every lane tests its pixel against the whole batch.
+// LDS, then every lane tests its pixel against the whole batch.  The count
+// pass also stores, per bin entry and wave, the 64-bit mask of covered
+// pixels; the fill pass reads those masks instead of testing coverage again
+// and skips the entries that cover nothing.
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
                                                   const uint32_t *__restrict__ bins,
-                                                  const int4 *__restrict__ face_v,
+                                                  const int4 *__restrict__ face_c,
                                                   const int4 *__restrict__ vscr, uint32_t *__restrict__ count,
-                                                  uint64_t cap) {
-    constexpr int NT = TW * TH;
+                                                  uint64_t cap, uint64_t *__restrict__ masks) {
+    constexpr int NT = TW * TH, NW = NT / 64;
     __shared__ CovSetup s_cov[NT];
     const int tile = blockIdx.x;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
     const int dx = SUB * lx, dy = SUB * ly;
+    const bool valid = (tx * TW + lx) < tl.W && (ty * TH + ly) < tl.H;
     // (bins beyond the capacity were not stored; the caller grows and redoes the frame)
     const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
     uint32_t n = 0;
@@ -251,34 +266,42 @@ __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__r
         const int m = (int)min((uint64_t)NT, b1 - base);
         if ((int)threadIdx.x < m) {
             CovSetup cs;
-            tri_setup<false>(face_v, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
+            tri_setup<false>(face_c, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
                              dummy);
             s_cov[threadIdx.x] = cs;
         }
         __syncthreads();
-        for (int j = 0; j < m; ++j) n += covers(s_cov[j], dx, dy) ? 1u : 0u;
+        uint64_t mine = 0;
+        for (int j = 0; j < m; ++j) {
+            const bool c = valid && covers(s_cov[j], dx, dy);
+            n += c ? 1u : 0u;
+            const uint64_t bm = __ballot(c);
+            if ((j & 63) == lane) mine = bm;
+            if ((j & 63) == 63 || j == m - 1) {
+                const int e = (j & ~63) + lane;
+                if (e < m) masks[(base + e) * NW + wave] = mine;
+            }
+        }
         __syncthreads();
     }
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    count[(size_t)tile * NT + threadIdx.x] = (px < tl.W && py < tl.H) ? n : 0u;
+    count[(size_t)tile * NT + threadIdx.x] = n;
 }
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int tile_lo, const uint64_t *__restrict__ tile_off,
                                                  const uint32_t *__restrict__ bins,
-                                                 const int4 *__restrict__ face_v, const int4 *__restrict__ vscr,
+                                                 const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
                                                  const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
-                                                 uint64_t cap) {
-    constexpr int NT = TW * TH;
-    __shared__ CovSetup s_cov[NT];
+                                                 uint64_t cap, const uint64_t *__restrict__ masks) {
+    constexpr int NT = TW * TH, NW = NT / 64;
     __shared__ KeySetup s_key[NT];
+    __shared__ uint64_t s_mask[NT * NW];
     const int tile = tile_lo + blockIdx.x;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
     const int dx = SUB * lx, dy = SUB * ly;
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool valid = px < tl.W && py < tl.H;
     const uint64_t pass_base = off[(size_t)tile_lo * NT];
     uint64_t *dst = rec + (off[(size_t)tile * NT + threadIdx.x] - pass_base);
     const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
@@ -286,20 +309,29 @@ __global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int tile_lo, const u
     for (uint64_t base = b0; base < b1; base += NT) {
         const int m = (int)min((uint64_t)NT, b1 - base);
         if ((int)threadIdx.x < m) {
-            CovSetup cs;
-            KeySetup ks;
-            tri_setup<true>(face_v, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
-            s_cov[threadIdx.x] = cs;
-            s_key[threadIdx.x] = ks;
+            uint64_t any = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint64_t mk = masks[(base + threadIdx.x) * NW + w];
+                s_mask[threadIdx.x * NW + w] = mk;
+                any |= mk;
+            }
+            if (any) {
+                CovSetup cs;
+                KeySetup ks;
+                tri_setup<true>(face_c, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
+                                ks);
+                s_key[threadIdx.x] = ks;
+            }
         }
         __syncthreads();
-        if (valid) {
-            for (int j = 0; j < m; ++j) {
-                if (covers(s_cov[j], dx, dy)) {
-                    const KeySetup &k = s_key[j];
-                    uint32_t key = depth_key(k, dx, dy);
-                    dst[n++] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
-                }
+        for (int j = 0; j < m; ++j) {
+            const uint64_t mk = s_mask[j * NW + wave];
+            if (mk == 0) continue;
+            if ((mk >> lane) & 1ull) {
+                const KeySetup &k = s_key[j];
+                const uint32_t key = depth_key(k, dx, dy);
+                dst[n++] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
             }
         }
         __syncthreads();
@@ -438,33 +470,40 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
                                                   const uint32_t *__restrict__ count, int t_sort,
                                                   uint32_t *__restrict__ lists, int64_t cap,
                                                   uint64_t *__restrict__ stats) {
-    int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // block-level aggregation in LDS, then one global atomic per class and block
+    __shared__ unsigned s_n[NCLASS];
+    __shared__ unsigned long long s_f[NCLASS], s_base[NCLASS];
+    if (threadIdx.x < NCLASS) {
+        s_n[threadIdx.x] = 0;
+        s_f[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int TP = tl.TW * tl.TH;
     int cls = -1;
+    uint32_t n = 0;
     if (p < p1) {
         int tile = (int)(p / TP), l = (int)(p % TP);
         int x = (tile % tl.ntx) * tl.TW + l % tl.TW;
         int y = (tile / tl.ntx) * tl.TH + l / tl.TW;
-        if (x < tl.W && y < tl.H) cls = length_class(count[p], t_sort);
+        if (x < tl.W && y < tl.H) {
+            n = count[p];
+            cls = length_class(n, t_sort);
+        }
     }
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int c = 0; c < NCLASS; ++c) {
-        unsigned long long m = __ballot(cls == c);
-        if (!m) continue;
-        unsigned long long base = 0;
-        int leader = __ffsll((long long)m) - 1;
-        if (lane == leader) base = atomicAdd((unsigned long long *)&stats[ST_CLASS + c], (unsigned long long)__popcll(m));
-        base = __shfl(base, leader);
-        if (cls == c) lists[(int64_t)c * cap + base + __popcll(m & lt)] = (uint32_t)p;
+    unsigned rank = 0;
+    if (cls >= 0) {
+        rank = atomicAdd(&s_n[cls], 1u);
+        atomicAdd(&s_f[cls], (unsigned long long)n);
     }
-    // fragments per class (for bandwidth accounting)
-    uint64_t nf = (cls >= 0) ? (uint64_t)count[p] : 0;
-    for (int c = 0; c < NCLASS; ++c) {
-        uint64_t v = (cls == c) ? nf : 0;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-        if (lane == 0 && v) atomicAdd((unsigned long long *)&stats[ST_CLASSF + c], (unsigned long long)v);
+    __syncthreads();
+    if (threadIdx.x < NCLASS) {
+        const int c = threadIdx.x;
+        s_base[c] = s_n[c] ? atomicAdd((unsigned long long *)&stats[ST_CLASS + c], (unsigned long long)s_n[c]) : 0ull;
+        if (s_f[c]) atomicAdd((unsigned long long *)&stats[ST_CLASSF + c], s_f[c]);
     }
+    __syncthreads();
+    if (cls >= 0) lists[(int64_t)cls * cap + s_base[cls] + rank] = (uint32_t)p;
 }
 
 void launch_classify(const Tiling &tl, int tile_lo, int tile_hi, const uint32_t *count, int t_sort,
@@ -506,42 +545,45 @@ void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, int4 *vscr, hipStream_t s) {
-    if (V > 0) k_transform<<<dim3((unsigned)((V + 255) / 256)), 256, 0, s>>>(posq, V, M, W, H, vscr);
+void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, VertRec *vert, int4 *vscr,
+                      hipStream_t s) {
+    if (V > 0) k_transform<<<dim3((unsigned)((V + 255) / 256)), 256, 0, s>>>(posq, V, M, W, H, vert, vscr);
 }
-void launch_tri_bin_count(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl, uint32_t *tile_cnt,
+void launch_tri_bin_count(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl, uint32_t *tile_cnt,
                           hipStream_t s) {
-    if (T > 0) k_tri_bin_count<<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_v, T, vscr, tl, tile_cnt);
+    if (T > 0)
+        k_tri_bin<false><<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_c, T, vscr, tl, tile_cnt, nullptr,
+                                                                          nullptr, 0);
 }
-void launch_tri_bin_scatter(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+void launch_tri_bin_scatter(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
                             const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             hipStream_t s) {
     if (T > 0)
-        k_tri_bin_scatter<<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_v, T, vscr, tl, tile_off, tile_fill,
-                                                                            bins, bin_cap);
+        k_tri_bin<true><<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_c, T, vscr, tl, tile_fill, tile_off,
+                                                                         bins, bin_cap);
 }
 
 #define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \
     if (tl.TW == TWv && tl.TH == THv) { CALL; return; }
 
 void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_v, const int4 *vscr, uint32_t *count, hipStream_t s) {
+                  const int4 *face_c, const int4 *vscr, uint32_t *count, uint64_t *masks, hipStream_t s) {
     dim3 g((unsigned)tl.ntiles);
-    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(tl, tile_off, bins, face_v, vscr, count, cap)));
+    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
 }
 
 void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *face_v, const int4 *vscr, const uint64_t *off, uint64_t *rec,
-                 hipStream_t s) {
+                 uint64_t cap, const int4 *face_c, const int4 *vscr, const uint64_t *off, uint64_t *rec,
+                 const uint64_t *masks, hipStream_t s) {
     if (tile_hi <= tile_lo) return;
     dim3 g((unsigned)(tile_hi - tile_lo));
-    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_v, vscr, off, rec, cap)));
+    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
 }
 
 }  // namespace hexfc

@@ -41,15 +41,38 @@ enum KernelId {
 
 struct Mat3q { long long m[3][4]; };  // rows x, y, w of M_q
 
+// One vertex: dequantised world position and importance t_v (set at upload),
+// then the current view's snapped screen position, inverse depth q and cull
+// flags (written by the transform).  32 bytes: one fragment's shading reads
+// whole vertices from few cache lines.
+struct __align__(32) VertRec {
+    float4 world;  // x, y, z, t_v
+    int4 scr;      // sx, sy, q, flags (1: behind the near plane, 2: outside the guard band)
+};
+// One face: corner ids c0..c3, importance t_e and LoD level (4 x u8) of the
+// edges k = (c_k, c_{k+1}).  48 bytes.
+struct __align__(16) FaceRec {
+    int4 c;
+    float4 te;
+    uint32_t lvl, pad0, pad1, pad2;
+};
+
 // Mesh arrays resident on the device.
 struct DevMesh {
-    const int4 *posq;       // [V] (X_q, Y_q, Z_q, 0)
-    const float4 *vpt;      // [V] (x, y, z, t_v) dequantised world position + importance
-    const int4 *face_v;     // [F] corner ids c0..c3
-    const uint32_t *face_lvl;  // [F] 4 x u8 edge levels, edge k = (c_k, c_{k+1})
-    const float4 *face_te;  // [F] edge importance
+    const int4 *posq;      // [V] (X_q, Y_q, Z_q, 0)
+    const VertRec *vert;   // [V]
+    const FaceRec *face;   // [F]
+    const int4 *face_c;    // [F] corner ids alone (dense, for the rasteriser)
+    const int4 *vscr;      // [V] screen part alone (dense, for the rasteriser)
     int64_t V, F;
 };
+
+// Blocks are dealt round-robin to the 8 XCDs (each with its own L2); remap a
+// block index so that every XCD works through one contiguous range.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
+    const uint32_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x * q + min(x, r) + i;
+}
 
 struct ShadeParams {
     float hc[3], inv_r;
@@ -63,17 +86,19 @@ struct Tiling {
 };
 
 // ---------------------------------------------------------------- launchers (geom.hip)
-void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, int4 *vscr, hipStream_t s);
-void launch_tri_bin_count(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, VertRec *vert, int4 *vscr,
+                      hipStream_t s);
+void launch_tri_bin_count(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
                           uint32_t *tile_cnt, hipStream_t s);
-void launch_tri_bin_scatter(const int4 *face_v, int64_t T, const int4 *vscr, const Tiling &tl,
+void launch_tri_bin_scatter(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
                             const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins,
                             uint64_t bin_cap, hipStream_t s);
+// masks: per bin entry and wave, the 64-bit coverage mask (written by count, read by fill)
 void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_v, const int4 *vscr, uint32_t *count, hipStream_t s);
+                  const int4 *face_c, const int4 *vscr, uint32_t *count, uint64_t *masks, hipStream_t s);
 void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off,
-                 const uint32_t *bins, uint64_t cap, const int4 *face_v, const int4 *vscr,
-                 const uint64_t *off, uint64_t *rec, hipStream_t s);
+                 const uint32_t *bins, uint64_t cap, const int4 *face_c, const int4 *vscr,
+                 const uint64_t *off, uint64_t *rec, const uint64_t *masks, hipStream_t s);
 // exclusive scan of n uint32 values into n+1 uint64 values (out[n] = total);
 // `stat` (nullable) receives the total.  tmp: scan_tmp_elems(n) uint64s.
 size_t scan_tmp_elems(int64_t n);
@@ -91,7 +116,6 @@ void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t
 struct ResolveArgs {
     Tiling tl;
     DevMesh mesh;
-    const int4 *vscr;
     const uint32_t *count;   // tile-major
     const uint64_t *off;     // tile-major
     const uint64_t *rec;     // workspace (pass-relative)

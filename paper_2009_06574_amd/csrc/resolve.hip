@@ -27,7 +27,7 @@ __device__ __forceinline__ float segdist(float px, float py, float pz, float ax,
     float ux = bx - ax, uy = by - ay, uz = bz - az;
     float wx = px - ax, wy = py - ay, wz = pz - az;
     float l2 = ux * ux + uy * uy + uz * uz;
-    float t = l2 > 0.f ? (wx * ux + wy * uy + wz * uz) / l2 : 0.f;
+    float t = l2 > 0.f ? (wx * ux + wy * uy + wz * uz) * __builtin_amdgcn_rcpf(l2) : 0.f;
     t = fminf(fmaxf(t, 0.f), 1.f);
     float dx = wx - t * ux, dy = wy - t * uy, dz = wz - t * uz;
     return sqrtf(dx * dx + dy * dy + dz * dz);
@@ -41,9 +41,10 @@ __device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x,
     const ShadeParams &sp = a.sp;
     const uint32_t f = tri >> 1;
     const bool t1 = tri & 1;
-    const int4 c = m.face_v[f];
-    const int ib = t1 ? c.z : c.y, ic = t1 ? c.w : c.z;
-    const int4 s0 = a.vscr[c.x], s1 = a.vscr[ib], s2 = a.vscr[ic];
+    const FaceRec F = m.face[f];
+    const int4 c = F.c;
+    const VertRec V0 = m.vert[c.x], V1 = m.vert[c.y], V2 = m.vert[c.z], V3 = m.vert[c.w];
+    const int4 s0 = V0.scr, s1 = t1 ? V2.scr : V1.scr, s2 = t1 ? V3.scr : V2.scr;
     // perspective-correct barycentrics: weight of vertex i = E_opp(i) * q_i,
     // the edge functions being exact in FP64
     const double X = (double)(SUB * x + SUB / 2), Y = (double)(SUB * y + SUB / 2);
@@ -51,10 +52,10 @@ __device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x,
     const double e1 = (double)(s0.x - s2.x) * (Y - s2.y) - (double)(s0.y - s2.y) * (X - s2.x);
     const double e2 = (double)(s1.x - s0.x) * (Y - s0.y) - (double)(s1.y - s0.y) * (X - s0.x);
     const double w0 = e0 * (double)s0.z, w1 = e1 * (double)s1.z, w2 = e2 * (double)s2.z;
-    const float inv = 1.0f / (float)(w0 + w1 + w2);
+    const float inv = __builtin_amdgcn_rcpf((float)(w0 + w1 + w2));
     const float l0 = (float)w0 * inv, l1 = (float)w1 * inv, l2 = (float)w2 * inv;
     // corners relative to corner 0 (exact: all are multiples of 2^-16)
-    const float4 P0 = m.vpt[c.x], P1 = m.vpt[c.y], P2 = m.vpt[c.z], P3 = m.vpt[c.w];
+    const float4 P0 = V0.world, P1 = V1.world, P2 = V2.world, P3 = V3.world;
     const float r1x = P1.x - P0.x, r1y = P1.y - P0.y, r1z = P1.z - P0.z;
     const float r2x = P2.x - P0.x, r2y = P2.y - P0.y, r2z = P2.z - P0.z;
     const float r3x = P3.x - P0.x, r3y = P3.y - P0.y, r3z = P3.z - P0.z;
@@ -74,8 +75,8 @@ __device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x,
     d[1] = segdist(px, py, pz, r1x, r1y, r1z, r2x, r2y, r2z);
     d[2] = segdist(px, py, pz, r2x, r2y, r2z, r3x, r3y, r3z);
     d[3] = segdist(px, py, pz, r3x, r3y, r3z, 0.f, 0.f, 0.f);
-    const uint32_t lv = m.face_lvl[f];
-    const float4 te4 = m.face_te[f];
+    const uint32_t lv = F.lvl;
+    const float4 te4 = F.te;
     const float te[4] = {te4.x, te4.y, te4.z, te4.w};
     // nearest visible edge of each set (ties: lower local edge index)
     float dF = INFINITY, dC = INFINITY, dA = d[0], tF = 0.f, tC = 0.f;
@@ -133,7 +134,7 @@ __global__ void __launch_bounds__(64) k_resolve_short(const uint32_t *__restrict
                                                       ResolveArgs a) {
     __shared__ uint64_t col[TS][64];
     const int lane = threadIdx.x;
-    const uint32_t idx = blockIdx.x * 64 + lane;
+    const uint32_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 64 + lane;
     if (idx >= npix) return;
     const uint32_t p = list[idx];
     const uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
@@ -209,7 +210,7 @@ template <int R>
 __global__ void __launch_bounds__(256) k_resolve_long(const uint32_t *__restrict__ list, uint32_t npix,
                                                       ResolveArgs a) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (wave >= npix) return;
     const uint32_t p = list[wave];
     const uint32_t n = a.count[p];
