@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-row-step", type=int, default=8)
+    ap.add_argument("--cpu-row-step", type=int, default=1)
     ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (scale for HBM counters) and exit")

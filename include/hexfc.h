@@ -153,6 +153,34 @@ hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
 hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const hexfc_hotspot *hot,
                                 const hexfc_style *style, float *rgba_out, void *stream);
 
+/* Batch of n views of the same viewport, each with its own camera, hotspot
+ * and style, rendered by one captured HIP graph: every stage (transform,
+ * binning, count, scan, classes, fill, resolve) runs once over all views, the
+ * resolve kernels being persistent grids that read the list classes from
+ * device memory.  The first call for a batch shape sizes the buffers
+ * (synchronising `stream` once) and captures the graph; later calls upload
+ * the view parameters and launch the graph without synchronising.  The
+ * workspace must hold the fragments of all n views.  rgba_out: device float
+ * [n][height][width][4].  A later call whose fragments outgrow the sizes
+ * captured is reported by hexfc_batch_status.  Errors: as hexfc_render_frame,
+ * EINVAL (viewports differ), EDEVICE (capture failed). */
+hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams, const hexfc_hotspot *hots,
+                                const hexfc_style *styles, float *rgba_out, void *stream);
+
+/* Waits for `stream`, then reports the fragments of the last batch (or frame)
+ * and whether it overflowed the captured sizes (its output is then invalid). */
+hexfc_status hexfc_batch_status(hexfc_ctx *ctx, uint64_t *fragments, int *overflow, void *stream);
+
+/* Autotuner: times every tile shape x t_sort in {0, 8, 16, 32, 64} on the
+ * given views (n == 1: hexfc_render_frame, else hexfc_render_batch; median of
+ * three runs), applies the fastest and records it in the JSON file at
+ * cache_path (NULL: no cache), keyed by device, viewport, mesh size and n; a
+ * cached entry is applied without timing.  choice_out (nullable) receives
+ * {tile_w, tile_h, t_sort}.  rgba_out is scratch output. */
+hexfc_status hexfc_autotune(hexfc_ctx *ctx, int n, const hexfc_camera *cams, const hexfc_hotspot *hots,
+                            const hexfc_style *styles, float *rgba_out, const char *cache_path, int *choice_out,
+                            void *stream);
+
 /* Tuning knobs (chosen by the autotuner): screen tile of tile_w x tile_h
  * pixels (8x8, 16x8, 16x16 or 32x8; one workgroup lane per pixel) and the
  * longest list sorted lane-per-pixel by insertion sort (t_sort in [0, 64];

@@ -382,6 +382,7 @@ int orc_frame_raster(const orc_mesh *m, const float *vp, int W, int H, int64_t n
     for (int64_t s = 0; s < fr->npix; ++s) {
         int32_t p = pix ? pix[s] : (int32_t)s;
         if (p < 0 || p >= P) { free(map); orc_frame_free(fr); return ORC_ERANGE; }
+        if (map[p] >= 0) { free(map); orc_frame_free(fr); return ORC_EINVAL; } /* repeated sample pixel */
         fr->pix[s] = p;
         map[p] = (int32_t)s;
     }

@@ -24,7 +24,8 @@ ABI_SYMBOLS = (
     "hexfc_create", "hexfc_destroy", "hexfc_set_workspace", "hexfc_upload_mesh",
     "hexfc_build_fragment_lists", "hexfc_resolve", "hexfc_render_frame", "hexfc_set_tuning",
     "hexfc_get_frame_stats", "hexfc_get_total_fragments", "hexfc_export_sorted_lists",
-    "hexfc_set_profiling", "hexfc_get_kernel_times",
+    "hexfc_set_profiling", "hexfc_get_kernel_times", "hexfc_render_batch", "hexfc_batch_status",
+    "hexfc_autotune",
     "hexfc_status_string", "hexfc_last_error",
 )
 
@@ -77,6 +78,9 @@ def load():
         "hexfc_export_sorted_lists": ([P, P, P, P, P], st),
         "hexfc_set_profiling": ([P, ct.c_int], st),
         "hexfc_get_kernel_times": ([P, P, P, ct.c_int], st),
+        "hexfc_render_batch": ([P, ct.c_int, P, P, P, P, P], st),
+        "hexfc_batch_status": ([P, P, P, P], st),
+        "hexfc_autotune": ([P, ct.c_int, P, P, P, P, ct.c_char_p, P, P], st),
         "hexfc_status_string": ([st], ct.c_char_p),
         "hexfc_last_error": ([P], ct.c_char_p),
     }
@@ -202,6 +206,42 @@ class Renderer:
                                                 ct.byref(style_struct(style)), _ptr(out), self._stream()))
         self.W, self.H = c.width, c.height
         return out
+
+    def render_batch(self, cams, hots, styles, out=None):
+        """n views of one viewport in one captured graph; returns [n, H, W, 4]."""
+        n = len(cams)
+        cc = (CCamera * n)(*[camera_struct(c) for c in cams])
+        hh = (CHotspot * n)(*[hotspot_struct(h) for h in hots])
+        ss = (CStyle * n)(*[style_struct(s) for s in styles])
+        W, H = cc[0].width, cc[0].height
+        if out is None:
+            out = self.torch.empty((n, H, W, 4), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hexfc_render_batch(self.ctx, n, ct.cast(cc, ct.c_void_p), ct.cast(hh, ct.c_void_p),
+                                                ct.cast(ss, ct.c_void_p), _ptr(out), self._stream()))
+        self.W, self.H = W, H
+        return out
+
+    def batch_status(self):
+        """(fragments, overflowed) of the last batch; waits for the stream."""
+        f = ct.c_uint64()
+        o = ct.c_int()
+        self._check(self.lib.hexfc_batch_status(self.ctx, ct.byref(f), ct.byref(o), self._stream()))
+        return int(f.value), bool(o.value)
+
+    def autotune(self, cams, hots, styles, cache_path=None, out=None):
+        """Choose tile shape and sort switch by timing; returns (tile_w, tile_h, t_sort)."""
+        n = len(cams)
+        cc = (CCamera * n)(*[camera_struct(c) for c in cams])
+        hh = (CHotspot * n)(*[hotspot_struct(h) for h in hots])
+        ss = (CStyle * n)(*[style_struct(s) for s in styles])
+        if out is None:
+            out = self.torch.empty((n, cc[0].height, cc[0].width, 4), dtype=self.torch.float32, device=self.device)
+        choice = (ct.c_int * 3)()
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.hexfc_autotune(self.ctx, n, ct.cast(cc, ct.c_void_p), ct.cast(hh, ct.c_void_p),
+                                            ct.cast(ss, ct.c_void_p), _ptr(out), path, ct.cast(choice, ct.c_void_p),
+                                            self._stream()))
+        return tuple(int(x) for x in choice)
 
     def export_sorted_lists(self):
         """(counts int32 [H*W], off int64 [H*W+1], rec int64 [F]) in row-major pixel order;

@@ -22,11 +22,13 @@ __device__ __forceinline__ long long floordiv_pos(long long n, long long d) {  /
 
 // Vertex transform (exact): clip = M_q (X_q, 2^16); screen position with 4
 // sub-pixel bits, round half up; inverse depth q = floor(2^56 / w_q).
-__global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq, int64_t V, Mat3q M,
-                                                   int W, int H, VertRec *__restrict__ vert,
-                                                   int4 *__restrict__ vscr) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
+__global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq, int64_t V, int64_t NVV,
+                                                   const ViewParams *__restrict__ views, int W, int H,
+                                                   VertRec *__restrict__ vert, int4 *__restrict__ vscr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NVV) return;
+    const int64_t view = i / V, v = i - view * V;
+    const Mat3q &M = views[view].M;
     int4 p = posq[v];
     long long X = p.x, Y = p.y, Z = p.z, O = 65536;
     long long cx = M.m[0][0] * X + M.m[0][1] * Y + M.m[0][2] * Z + M.m[0][3] * O;
@@ -47,8 +49,8 @@ __global__ void __launch_bounds__(256) k_transform(const int4 *__restrict__ posq
             out.z = (int)(QNUM / cw);
         }
     }
-    vert[v].scr = out;  // for shading
-    vscr[v] = out;      // dense copy for the rasteriser
+    vert[i].scr = out;  // for shading
+    vscr[i] = out;      // dense copy for the rasteriser
 }
 
 // Triangle t of the face list: corners (c0,c1,c2) or (c0,c2,c3).
@@ -95,23 +97,25 @@ __device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_c, 
 // that hit the same tile are merged into one atomic (leader election by
 // ballot), and each gets its rank inside the merged group.
 template <bool SCATTER>
-__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t T,
-                                                 const int4 *__restrict__ vscr, Tiling tl,
+__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t T, int64_t NVT,
+                                                 const int4 *__restrict__ vscr, int64_t V, Tiling tl,
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
                                                  uint32_t *__restrict__ bins, uint64_t cap) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t view = i < NVT ? i / T : 0, t = i - view * T;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
-    const bool ok = t < T && tri_tile_range(face_c, vscr, t, tl, tx0, tx1, ty0, ty1);
+    const bool ok = i < NVT && tri_tile_range(face_c, vscr + view * V, t, tl, tx0, tx1, ty0, ty1);
+    const int64_t tile0 = view * tl.ntiles;
     const int nx = ok ? tx1 - tx0 + 1 : 1;
     const int n = ok ? nx * (ty1 - ty0 + 1) : 0;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (int k = 0; __any(k < n); ++k) {
-        const int tile = (k < n) ? (ty0 + k / nx) * tl.ntx + tx0 + k % nx : -1;
+        const int64_t tile = (k < n) ? tile0 + (ty0 + k / nx) * tl.ntx + tx0 + k % nx : -1;
         unsigned long long pend = __ballot(tile >= 0);
         while (pend) {
             const int leader = __ffsll((long long)pend) - 1;
-            const int lead_tile = __shfl(tile, leader);
+            const int64_t lead_tile = __shfl(tile, leader);
             const unsigned long long same = __ballot(tile == lead_tile);
             unsigned base = 0;
             if (lane == leader) base = atomicAdd(&tile_ctr[lead_tile], (unsigned)__popcll(same));
@@ -247,11 +251,15 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
                                                   const uint32_t *__restrict__ bins,
                                                   const int4 *__restrict__ face_c,
-                                                  const int4 *__restrict__ vscr, uint32_t *__restrict__ count,
-                                                  uint64_t cap, uint64_t *__restrict__ masks) {
+                                                  const int4 *__restrict__ vscr, int64_t V,
+                                                  uint32_t *__restrict__ count, uint64_t cap,
+                                                  uint64_t *__restrict__ masks) {
     constexpr int NT = TW * TH, NW = NT / 64;
     __shared__ CovSetup s_cov[NT];
-    const int tile = blockIdx.x;
+    const int64_t g = blockIdx.x;  // global tile
+    const int64_t view = g / tl.ntiles;
+    const int tile = (int)(g - view * tl.ntiles);
+    vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -259,7 +267,7 @@ __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__r
     const int dx = SUB * lx, dy = SUB * ly;
     const bool valid = (tx * TW + lx) < tl.W && (ty * TH + ly) < tl.H;
     // (bins beyond the capacity were not stored; the caller grows and redoes the frame)
-    const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
+    const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     uint32_t n = 0;
     KeySetup dummy;
     for (uint64_t base = b0; base < b1; base += NT) {
@@ -284,27 +292,34 @@ __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__r
         }
         __syncthreads();
     }
-    count[(size_t)tile * NT + threadIdx.x] = n;
+    count[(size_t)g * NT + threadIdx.x] = n;
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int tile_lo, const uint64_t *__restrict__ tile_off,
+__global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
                                                  const uint32_t *__restrict__ bins,
                                                  const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
-                                                 const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
-                                                 uint64_t cap, const uint64_t *__restrict__ masks) {
+                                                 int64_t V, const uint64_t *__restrict__ off,
+                                                 uint64_t *__restrict__ rec, uint64_t rec_cap, uint64_t cap,
+                                                 const uint64_t *__restrict__ masks) {
     constexpr int NT = TW * TH, NW = NT / 64;
     __shared__ KeySetup s_key[NT];
     __shared__ uint64_t s_mask[NT * NW];
-    const int tile = tile_lo + blockIdx.x;
+    const int64_t g = g0 + blockIdx.x;  // global tile
+    const int64_t view = g / tl.ntiles;
+    const int tile = (int)(g - view * tl.ntiles);
+    vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
     const int dx = SUB * lx, dy = SUB * ly;
-    const uint64_t pass_base = off[(size_t)tile_lo * NT];
-    uint64_t *dst = rec + (off[(size_t)tile * NT + threadIdx.x] - pass_base);
-    const uint64_t b0 = min(tile_off[tile], cap), b1 = min(tile_off[tile + 1], cap);
+    const uint64_t pass_base = off[(size_t)g0 * NT];
+    const uint64_t first = off[(size_t)g * NT + threadIdx.x] - pass_base;
+    uint64_t *dst = rec + first;
+    // records beyond the workspace are dropped (the frame is then reported as overflowed)
+    const uint64_t room = first < rec_cap ? rec_cap - first : 0;
+    const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     uint32_t n = 0;
     for (uint64_t base = b0; base < b1; base += NT) {
         const int m = (int)min((uint64_t)NT, b1 - base);
@@ -331,7 +346,8 @@ __global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int tile_lo, const u
             if ((mk >> lane) & 1ull) {
                 const KeySetup &k = s_key[j];
                 const uint32_t key = depth_key(k, dx, dy);
-                dst[n++] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
+                if (n < room) dst[n] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
+                ++n;
             }
         }
         __syncthreads();
@@ -483,7 +499,8 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
     int cls = -1;
     uint32_t n = 0;
     if (p < p1) {
-        int tile = (int)(p / TP), l = (int)(p % TP);
+        const int64_t lp = p % ((int64_t)tl.ntiles * TP);  // pixel within its view
+        int tile = (int)(lp / TP), l = (int)(lp % TP);
         int x = (tile % tl.ntx) * tl.TW + l % tl.TW;
         int y = (tile / tl.ntx) * tl.TH + l / tl.TW;
         if (x < tl.W && y < tl.H) {
@@ -506,10 +523,10 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
     if (cls >= 0) lists[(int64_t)cls * cap + s_base[cls] + rank] = (uint32_t)p;
 }
 
-void launch_classify(const Tiling &tl, int tile_lo, int tile_hi, const uint32_t *count, int t_sort,
+void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *count, int t_sort,
                      uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s) {
     const int TP = tl.TW * tl.TH;
-    int64_t p0 = (int64_t)tile_lo * TP, p1 = (int64_t)tile_hi * TP;
+    int64_t p0 = g0 * TP, p1 = g1 * TP;
     int64_t n = p1 - p0;
     if (n <= 0) return;
     k_classify<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, p0, p1, count, t_sort, cls_lists, cls_cap, stats);
@@ -545,45 +562,52 @@ void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, VertRec *vert, int4 *vscr,
-                      hipStream_t s) {
-    if (V > 0) k_transform<<<dim3((unsigned)((V + 255) / 256)), 256, 0, s>>>(posq, V, M, W, H, vert, vscr);
+void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *views, int W, int H, VertRec *vert,
+                      int4 *vscr, hipStream_t s) {
+    const int64_t n = V * nv;
+    if (n > 0) k_transform<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(posq, V, n, views, W, H, vert, vscr);
 }
-void launch_tri_bin_count(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl, uint32_t *tile_cnt,
-                          hipStream_t s) {
-    if (T > 0)
-        k_tri_bin<false><<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_c, T, vscr, tl, tile_cnt, nullptr,
-                                                                          nullptr, 0);
+void launch_tri_bin_count(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+                          uint32_t *tile_cnt, hipStream_t s) {
+    const int64_t n = T * nv;
+    if (n > 0)
+        k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, T, n, vscr, V, tl, tile_cnt,
+                                                                          nullptr, nullptr, 0);
 }
-void launch_tri_bin_scatter(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
+void launch_tri_bin_scatter(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                             const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             hipStream_t s) {
-    if (T > 0)
-        k_tri_bin<true><<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(face_c, T, vscr, tl, tile_fill, tile_off,
-                                                                         bins, bin_cap);
+    const int64_t n = T * nv;
+    if (n > 0)
+        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, T, n, vscr, V, tl, tile_fill,
+                                                                         tile_off, bins, bin_cap);
 }
 
 #define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \
     if (tl.TW == TWv && tl.TH == THv) { CALL; return; }
 
-void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_c, const int4 *vscr, uint32_t *count, uint64_t *masks, hipStream_t s) {
-    dim3 g((unsigned)tl.ntiles);
-    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(tl, tile_off, bins, face_c, vscr, count, cap, masks)));
+void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
+                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, hipStream_t s) {
+    dim3 g((unsigned)((int64_t)tl.ntiles * nv));
+#define ARGS tl, tile_off, bins, face_c, vscr, V, count, cap, masks
+    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(ARGS)));
+#undef ARGS
 }
 
-void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *face_c, const int4 *vscr, const uint64_t *off, uint64_t *rec,
-                 const uint64_t *masks, hipStream_t s) {
-    if (tile_hi <= tile_lo) return;
-    dim3 g((unsigned)(tile_hi - tile_lo));
-    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(tl, tile_lo, tile_off, bins, face_c, vscr, off, rec, cap, masks)));
+void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
+                 uint64_t cap, const int4 *face_c, const int4 *vscr, int64_t V, const uint64_t *off, uint64_t *rec,
+                 uint64_t rec_cap, const uint64_t *masks, hipStream_t s) {
+    if (g1 <= g0) return;
+    dim3 g((unsigned)(g1 - g0));
+#define ARGS tl, g0, tile_off, bins, face_c, vscr, V, off, rec, rec_cap, cap, masks
+    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(ARGS)));
+#undef ARGS
 }
 
 }  // namespace hexfc

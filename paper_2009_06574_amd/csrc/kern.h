@@ -1,5 +1,10 @@
 // kern.h -- internal declarations shared by the library's translation units
 // (device data layout, kernel launchers).  Not part of the public ABI.
+//
+// Every per-frame kernel handles a batch of NV views of the same size: view v
+// owns tiles [v*ntiles, (v+1)*ntiles), pixels [v*P_t, (v+1)*P_t) in
+// tile-major order (P_t = ntiles * TW * TH), and vertices [v*V, (v+1)*V) of
+// the screen arrays.  A single frame is a batch of one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,7 +12,7 @@
 namespace hexfc {
 
 // ---------------------------------------------------------------- constants
-constexpr int SUB = 16;                      // sub-pixels per pixel (4 bits)
+constexpr int SUB = 16;                         // sub-pixels per pixel (4 bits)
 constexpr int64_t W_NEAR_Q = int64_t(1) << 32;  // w_q below this culls (w < 1/16)
 constexpr int64_t GUARD = int64_t(1) << 17;     // |s| >= GUARD culls
 constexpr int64_t QNUM = int64_t(1) << 56;      // q = floor(QNUM / w_q)
@@ -20,7 +25,7 @@ constexpr int MAX_LIST = 2048;                  // longest list a resolve kernel
 // elements (classes 1..6); class 7 = longer than MAX_LIST (an error).
 constexpr int NCLASS = 8;
 
-// device-side statistics written by the kernels and read back once per frame
+// device-side statistics written by the kernels (read back by the host)
 enum StatSlot {
     ST_BINS = 0,      // bin entries needed
     ST_FRAGS = 1,     // total fragments
@@ -42,9 +47,9 @@ enum KernelId {
 struct Mat3q { long long m[3][4]; };  // rows x, y, w of M_q
 
 // One vertex: dequantised world position and importance t_v (set at upload),
-// then the current view's snapped screen position, inverse depth q and cull
-// flags (written by the transform).  32 bytes: one fragment's shading reads
-// whole vertices from few cache lines.
+// then the view's snapped screen position, inverse depth q and cull flags
+// (written by the transform).  32 bytes: one fragment's shading reads whole
+// vertices from few cache lines.
 struct __align__(32) VertRec {
     float4 world;  // x, y, z, t_v
     int4 scr;      // sx, sy, q, flags (1: behind the near plane, 2: outside the guard band)
@@ -57,13 +62,31 @@ struct __align__(16) FaceRec {
     uint32_t lvl, pad0, pad1, pad2;
 };
 
-// Mesh arrays resident on the device.
+// Shading constants of one view (hotspot and style).
+struct ShadeParams {
+    float hc[3], inv_r;
+    float w_base, k_focus, halo_w, halo_a, darken, s, bright, delta;
+    int lod;
+    float lo[3], hi[3], a_lo, a_hi, bg[3];
+};
+
+// Everything per view that the kernels read from device memory.
+struct ViewParams {
+    Mat3q M;
+    ShadeParams sp;
+};
+
+struct Tiling {
+    int W, H, TW, TH, ntx, nty, ntiles;
+};
+
+// Mesh arrays resident on the device plus the per-view screen arrays.
 struct DevMesh {
     const int4 *posq;      // [V] (X_q, Y_q, Z_q, 0)
-    const VertRec *vert;   // [V]
+    const VertRec *vert;   // [NV*V] world part replicated per view, screen part per view
     const FaceRec *face;   // [F]
     const int4 *face_c;    // [F] corner ids alone (dense, for the rasteriser)
-    const int4 *vscr;      // [V] screen part alone (dense, for the rasteriser)
+    const int4 *vscr;      // [NV*V] screen part alone (dense, for the rasteriser)
     int64_t V, F;
 };
 
@@ -74,40 +97,30 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
     return x * q + min(x, r) + i;
 }
 
-struct ShadeParams {
-    float hc[3], inv_r;
-    float w_base, k_focus, halo_w, halo_a, darken, s, bright, delta;
-    int lod;
-    float lo[3], hi[3], a_lo, a_hi, bg[3];
-};
-
-struct Tiling {
-    int W, H, TW, TH, ntx, nty, ntiles;
-};
-
 // ---------------------------------------------------------------- launchers (geom.hip)
-void launch_transform(const int4 *posq, int64_t V, const Mat3q &M, int W, int H, VertRec *vert, int4 *vscr,
-                      hipStream_t s);
-void launch_tri_bin_count(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
+void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *views, int W, int H, VertRec *vert,
+                      int4 *vscr, hipStream_t s);
+void launch_tri_bin_count(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                           uint32_t *tile_cnt, hipStream_t s);
-void launch_tri_bin_scatter(const int4 *face_c, int64_t T, const int4 *vscr, const Tiling &tl,
-                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins,
-                            uint64_t bin_cap, hipStream_t s);
+void launch_tri_bin_scatter(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
+                            hipStream_t s);
 // masks: per bin entry and wave, the 64-bit coverage mask (written by count, read by fill)
-void launch_count(const Tiling &tl, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_c, const int4 *vscr, uint32_t *count, uint64_t *masks, hipStream_t s);
-void launch_fill(const Tiling &tl, int tile_lo, int tile_hi, const uint64_t *tile_off,
-                 const uint32_t *bins, uint64_t cap, const int4 *face_c, const int4 *vscr,
-                 const uint64_t *off, uint64_t *rec, const uint64_t *masks, hipStream_t s);
+void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
+                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, hipStream_t s);
+// fill global tiles [g0, g1); records are relative to off[g0 * TP]; at most rec_cap records
+void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
+                 uint64_t cap, const int4 *face_c, const int4 *vscr, int64_t V, const uint64_t *off, uint64_t *rec,
+                 uint64_t rec_cap, const uint64_t *masks, hipStream_t s);
 // exclusive scan of n uint32 values into n+1 uint64 values (out[n] = total);
 // `stat` (nullable) receives the total.  tmp: scan_tmp_elems(n) uint64s.
 size_t scan_tmp_elems(int64_t n);
-void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t *tmp,
-                         uint64_t *stat, hipStream_t s);
-void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, uint64_t *stats,
-                 hipStream_t s);
-void launch_classify(const Tiling &tl, int tile_lo, int tile_hi, const uint32_t *count,
-                     int t_sort, uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s);
+void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t *tmp, uint64_t *stat,
+                         hipStream_t s);
+void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, uint64_t *stats, hipStream_t s);
+// pixels of global tiles [g0, g1) into per-class lists (global pixel ids)
+void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *count, int t_sort,
+                     uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s);
 void launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t *count_rm, hipStream_t s);
@@ -116,16 +129,19 @@ void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t
 struct ResolveArgs {
     Tiling tl;
     DevMesh mesh;
-    const uint32_t *count;   // tile-major
-    const uint64_t *off;     // tile-major
-    const uint64_t *rec;     // workspace (pass-relative)
-    int64_t pass_p0;         // first pixel (tile-major) of the pass; records are relative to off[pass_p0]
-    ShadeParams sp;
-    float *rgba;             // row-major, nullable (sort-only)
-    uint64_t *sorted_out;    // nullable: sorted records, row-major CSR
-    const uint64_t *off_rm;  // row-major offsets for sorted_out
+    const ViewParams *views;  // [NV]
+    const uint32_t *count;    // global tile-major pixels
+    const uint64_t *off;
+    const uint64_t *rec;      // workspace (pass-relative)
+    uint64_t rec_cap;         // records the workspace holds
+    int64_t pass_p0;          // first global pixel of the pass; records are relative to off[pass_p0]
+    float *rgba;              // [NV][H][W][4], nullable (sort-only)
+    uint64_t *sorted_out;     // nullable: sorted records, row-major CSR (single view)
+    const uint64_t *off_rm;   // row-major offsets for sorted_out
 };
-void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, int t_sort,
+// npix > 0: exact grid for that many pixels.  npix_dev != nullptr: a fixed,
+// persistent grid that reads the class size from device memory (graph replay).
+void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
                           const ResolveArgs &a, hipStream_t s);
 
 }  // namespace hexfc

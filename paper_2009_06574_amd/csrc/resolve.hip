@@ -36,14 +36,13 @@ __device__ __forceinline__ float segdist(float px, float py, float pz, float ax,
 // Premultiplied colour and opacity of one fragment: triangle `tri` at pixel
 // (x, y).  Eq. 1 (edges, with the focus-edge halo and darkening), Eq. 2
 // (accentuation), Eq. 3 (face opacity), Eq. 4 (edge/face blend).
-__device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x, int y) {
-    const DevMesh &m = a.mesh;
-    const ShadeParams &sp = a.sp;
+__device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restrict__ vert, const ShadeParams &sp,
+                                      uint32_t tri, int x, int y) {
     const uint32_t f = tri >> 1;
     const bool t1 = tri & 1;
     const FaceRec F = m.face[f];
     const int4 c = F.c;
-    const VertRec V0 = m.vert[c.x], V1 = m.vert[c.y], V2 = m.vert[c.z], V3 = m.vert[c.w];
+    const VertRec V0 = vert[c.x], V1 = vert[c.y], V2 = vert[c.z], V3 = vert[c.w];
     const int4 s0 = V0.scr, s1 = t1 ? V2.scr : V1.scr, s2 = t1 ? V3.scr : V2.scr;
     // perspective-correct barycentrics: weight of vertex i = E_opp(i) * q_i,
     // the edge functions being exact in FP64
@@ -119,55 +118,73 @@ __device__ __forceinline__ Frag shade(const ResolveArgs &a, uint32_t tri, int x,
     return o;
 }
 
-__device__ __forceinline__ void pixel_xy(const Tiling &tl, uint32_t p, int &x, int &y) {
+// Global pixel id -> view and pixel coordinates.
+struct PixelRef {
+    int64_t view;
+    int x, y;
+};
+__device__ __forceinline__ PixelRef pixel_ref(const Tiling &tl, uint32_t gp) {
     const int TP = tl.TW * tl.TH;
+    const int64_t pt = (int64_t)tl.ntiles * TP;
+    PixelRef r;
+    r.view = gp / pt;
+    const int64_t p = gp - r.view * pt;
     const int tile = (int)(p / TP), l = (int)(p % TP);
-    x = (tile % tl.ntx) * tl.TW + l % tl.TW;
-    y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+    r.x = (tile % tl.ntx) * tl.TW + l % tl.TW;
+    r.y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+    return r;
 }
 
 constexpr float T_EPS = 9.5367431640625e-07f;  // 2^-20: stop once 1 - A is below it
 
 // ------------------------------------------------------------------ short lists
+// One lane per pixel.  With npix_dev set the grid is persistent: it strides
+// over the class list whose size it reads from device memory.
 template <int TS>
 __global__ void __launch_bounds__(64) k_resolve_short(const uint32_t *__restrict__ list, uint32_t npix,
-                                                      ResolveArgs a) {
+                                                      const uint64_t *__restrict__ npix_dev, ResolveArgs a) {
     __shared__ uint64_t col[TS][64];
     const int lane = threadIdx.x;
-    const uint32_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 64 + lane;
-    if (idx >= npix) return;
-    const uint32_t p = list[idx];
-    const uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
-    const uint64_t *src = a.rec + (a.off[p] - a.off[a.pass_p0]);
-    for (uint32_t i = 0; i < n; ++i) {
-        const uint64_t r = src[i];
-        int j = (int)i;
-        while (j > 0 && col[j - 1][lane] > r) {
-            col[j][lane] = col[j - 1][lane];
-            --j;
-        }
-        col[j][lane] = r;
-    }
-    int x, y;
-    pixel_xy(a.tl, p, x, y);
-    if (a.sorted_out) {
-        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)y * a.tl.W + x];
-        for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
-    }
-    if (a.rgba) {
-        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    const uint32_t total = npix_dev ? (uint32_t)*npix_dev : npix;
+    for (uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x); chunk * 64 < total; chunk += gridDim.x) {
+        const uint32_t idx = chunk * 64 + lane;
+        if (idx >= total) continue;
+        const uint32_t p = list[idx];
+        uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
+        const uint64_t first = a.off[p] - a.off[a.pass_p0];
+        if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
+        const uint64_t *src = a.rec + first;
         for (uint32_t i = 0; i < n; ++i) {
-            const float T = 1.f - A;
-            if (T < T_EPS) break;
-            const Frag fr = shade(a, (uint32_t)(col[i][lane] & 0xffffffffu), x, y);
-            C0 += T * fr.r;
-            C1 += T * fr.g;
-            C2 += T * fr.b;
-            A += T * fr.a;
+            const uint64_t r = src[i];
+            int j = (int)i;
+            while (j > 0 && col[j - 1][lane] > r) {
+                col[j][lane] = col[j - 1][lane];
+                --j;
+            }
+            col[j][lane] = r;
         }
-        const float T = 1.f - A;
-        float4 out = make_float4(C0 + T * a.sp.bg[0], C1 + T * a.sp.bg[1], C2 + T * a.sp.bg[2], A);
-        reinterpret_cast<float4 *>(a.rgba)[(int64_t)y * a.tl.W + x] = out;
+        const PixelRef pr = pixel_ref(a.tl, p);
+        if (a.sorted_out) {
+            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+            for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
+        }
+        if (a.rgba) {
+            const ShadeParams &sp = a.views[pr.view].sp;
+            const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+            for (uint32_t i = 0; i < n; ++i) {
+                const float T = 1.f - A;
+                if (T < T_EPS) break;
+                const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(col[i][lane] & 0xffffffffu), pr.x, pr.y);
+                C0 += T * fr.r;
+                C1 += T * fr.g;
+                C2 += T * fr.b;
+                A += T * fr.a;
+            }
+            const float T = 1.f - A;
+            float4 out = make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
+            reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = out;
+        }
     }
 }
 
@@ -208,83 +225,92 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[R], int lane) {
 
 template <int R>
 __global__ void __launch_bounds__(256) k_resolve_long(const uint32_t *__restrict__ list, uint32_t npix,
-                                                      ResolveArgs a) {
+                                                      const uint64_t *__restrict__ npix_dev, ResolveArgs a) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (wave >= npix) return;
-    const uint32_t p = list[wave];
-    const uint32_t n = a.count[p];
-    const uint64_t *src = a.rec + (a.off[p] - a.off[a.pass_p0]);
-    uint64_t v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t e = lane * R + r;
-        v[r] = e < n ? src[e] : ~0ull;
-    }
-    bitonic_sort<R>(v, lane);
-    int x, y;
-    pixel_xy(a.tl, p, x, y);
-    if (a.sorted_out) {
-        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)y * a.tl.W + x];
+    const uint32_t total = npix_dev ? (uint32_t)*npix_dev : npix;
+    for (uint32_t blk = xcd_contiguous(blockIdx.x, gridDim.x); blk * 4 < total; blk += gridDim.x) {
+        const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
+        if (wave >= total) continue;
+        const uint32_t p = list[wave];
+        uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
+        const uint64_t first = a.off[p] - a.off[a.pass_p0];
+        if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
+        const uint64_t *src = a.rec + first;
+        uint64_t v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t e = lane * R + r;
-            if (e < n) dst[e] = v[r];
+            v[r] = e < n ? src[e] : ~0ull;
         }
-    }
-    if (a.rgba) {
-        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+        bitonic_sort<R>(v, lane);
+        const PixelRef pr = pixel_ref(a.tl, p);
+        if (a.sorted_out) {
+            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t e = lane * R + r;
-            if (e < n) {
-                const Frag fr = shade(a, (uint32_t)(v[r] & 0xffffffffu), x, y);
-                const float T = 1.f - A;
-                C0 += T * fr.r;
-                C1 += T * fr.g;
-                C2 += T * fr.b;
-                A += T * fr.a;
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e = lane * R + r;
+                if (e < n) dst[e] = v[r];
             }
         }
-        // ordered reduction: lane l's run precedes lane l+1's
+        if (a.rgba) {
+            const ShadeParams &sp = a.views[pr.view].sp;
+            const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o),
-                        qa = __shfl_down(A, o);
-            if ((lane & (2 * o - 1)) == 0) {
-                const float T = 1.f - A;
-                C0 += T * q0;
-                C1 += T * q1;
-                C2 += T * q2;
-                A += T * qa;
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e = lane * R + r;
+                if (e < n) {
+                    const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(v[r] & 0xffffffffu), pr.x, pr.y);
+                    const float T = 1.f - A;
+                    C0 += T * fr.r;
+                    C1 += T * fr.g;
+                    C2 += T * fr.b;
+                    A += T * fr.a;
+                }
             }
-        }
-        if (lane == 0) {
-            const float T = 1.f - A;
-            float4 out = make_float4(C0 + T * a.sp.bg[0], C1 + T * a.sp.bg[1], C2 + T * a.sp.bg[2], A);
-            reinterpret_cast<float4 *>(a.rgba)[(int64_t)y * a.tl.W + x] = out;
+            // ordered reduction: lane l's run precedes lane l+1's
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o),
+                            qa = __shfl_down(A, o);
+                if ((lane & (2 * o - 1)) == 0) {
+                    const float T = 1.f - A;
+                    C0 += T * q0;
+                    C1 += T * q1;
+                    C2 += T * q2;
+                    A += T * qa;
+                }
+            }
+            if (lane == 0) {
+                const float T = 1.f - A;
+                float4 out = make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
+                reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = out;
+            }
         }
     }
 }
 
-void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, int t_sort, const ResolveArgs &a,
-                          hipStream_t s) {
-    if (npix == 0) return;
+// persistent grids: enough blocks to fill the chip several times over
+constexpr unsigned PERSIST_SHORT = 256 * 16, PERSIST_LONG = 256 * 8;
+
+void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
+                          const ResolveArgs &a, hipStream_t s) {
+    if (npix == 0 && !npix_dev) return;
     if (cls == 0) {
-        dim3 g((npix + 63) / 64);
-        if (t_sort <= 16) k_resolve_short<16><<<g, 64, 0, s>>>(pix_list, npix, a);
-        else if (t_sort <= 32) k_resolve_short<32><<<g, 64, 0, s>>>(pix_list, npix, a);
-        else k_resolve_short<64><<<g, 64, 0, s>>>(pix_list, npix, a);
+        dim3 g(npix_dev ? PERSIST_SHORT : (npix + 63) / 64);
+        if (t_sort <= 16) k_resolve_short<16><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
+        else if (t_sort <= 32) k_resolve_short<32><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
+        else k_resolve_short<64><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
         return;
     }
-    dim3 g((npix + 3) / 4);
+    dim3 g(npix_dev ? PERSIST_LONG : (npix + 3) / 4);
     switch (cls) {
-        case 1: k_resolve_long<1><<<g, 256, 0, s>>>(pix_list, npix, a); break;
-        case 2: k_resolve_long<2><<<g, 256, 0, s>>>(pix_list, npix, a); break;
-        case 3: k_resolve_long<4><<<g, 256, 0, s>>>(pix_list, npix, a); break;
-        case 4: k_resolve_long<8><<<g, 256, 0, s>>>(pix_list, npix, a); break;
-        case 5: k_resolve_long<16><<<g, 256, 0, s>>>(pix_list, npix, a); break;
-        case 6: k_resolve_long<32><<<g, 256, 0, s>>>(pix_list, npix, a); break;
+        case 1: k_resolve_long<1><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
+        case 2: k_resolve_long<2><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
+        case 3: k_resolve_long<4><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
+        case 4: k_resolve_long<8><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
+        case 5: k_resolve_long<16><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
+        case 6: k_resolve_long<32><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
         default: break;
     }
 }

@@ -294,6 +294,12 @@ def test_permutation_invariance(orc, cfg0_small):
     assert np.abs(rgba1 - rgba2)[~tie].max() < 1e-12
 
 
+def test_repeated_sample_pixels_rejected(orc, cfg0_small):
+    d = cfg0_small
+    with pytest.raises(orc.OracleError):
+        orc.Frame.from_camera(d["om"], d["cam"], pixels=np.array([5, 7, 5], np.int32))
+
+
 def test_tile_order_independence_of_sample_sets(orc, cfg0_small):
     """Rendering a pixel subset gives the same lists as the full frame."""
     d = cfg0_small
