@@ -67,6 +67,8 @@ def _load():
     lib.orc_frame_cands.argtypes = [P, P, P]
     lib.orc_shade_one.argtypes = [P, i64, i64, ct.c_uint32, P, P, ct.c_uint, P]
     lib.orc_num_threads.restype = ct.c_int
+    lib.orc_frame_tail.argtypes = [P, P, P, ct.c_int, ct.c_double, ct.c_double, P, P, P, P]
+    lib.orc_frame_tail.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -207,10 +209,38 @@ class Frame:
         _load().orc_shade_one(self._h, int(i), int(j), int(tri), _ptr(hv), _ptr(sv), int(flip), _ptr(out))
         return out
 
+    def tail(self, hotspot, style, K, w0, w1):
+        """Head composite, tail features and exact tail target per sample pixel
+        (learned-tail definition in hexfc_oracle.c): (head, feat, target, has)."""
+        hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
+        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        head = np.zeros((self.npix, 4))
+        feat = np.zeros((self.npix, 9))
+        target = np.zeros((self.npix, 4))
+        has = np.zeros(self.npix, np.uint8)
+        rc = _load().orc_frame_tail(self._h, _ptr(hv), _ptr(sv), int(K), float(w0), float(w1), _ptr(head),
+                                    _ptr(feat), _ptr(target), _ptr(has))
+        if rc != 0:
+            raise OracleError(f"orc_frame_tail failed: {rc}")
+        return head, feat, target, has.astype(bool)
+
     def __del__(self):
         if getattr(self, "_h", None):
             _load().orc_frame_free(self._h)
             self._h = None
+
+
+def view_depth_range(mesh_pos_q, view_proj):
+    """[w0, w1]: range of the clip w of the 8 corners of the bbox of the
+    (dequantised) vertex positions, computed with the float camera matrix."""
+    P = np.asarray(mesh_pos_q, dtype=np.float64) / 65536.0
+    lo, hi = P.min(axis=0), P.max(axis=0)
+    M = np.asarray(view_proj, dtype=np.float32).astype(np.float64).reshape(4, 4)
+    ws = []
+    for c in range(8):
+        x = np.array([hi[0] if c & 1 else lo[0], hi[1] if c & 2 else lo[1], hi[2] if c & 4 else lo[2], 1.0])
+        ws.append(float(M[3] @ x))
+    return min(ws), max(ws)
 
 
 def render(mesh_synth, cam, hot, style, pixels=None):

@@ -699,3 +699,80 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------- learned tail
+ * Head/tail split of a sorted list (the approximate-compositing direction of
+ * Section 8): the first K fragments are blended exactly (head); the tail
+ * (fragments K..n-1) is summarised by 9 features computed from a cheap proxy
+ * shading, and its exact composite is the regression target.
+ *   proxy fragment: alpha~ = ahat(tbar) * min(|c_face - h| / r, 1)^4,
+ *                   colour~ = TF(tbar), with c_face the mean of the face's
+ *                   corners and tbar the mean corner importance;
+ *   depth z = (w - w0) / (w1 - w0) clamped to [0,1], w = 2^20 / key the view
+ *   depth of the fragment, [w0, w1] the view-depth range of the mesh bbox;
+ *   features: log1p(n_tail), sum alpha~, sum alpha~ z^k / sum alpha~ (k=1..4),
+ *   sum alpha~ colour~ / sum alpha~ (3).
+ * Outputs per sample pixel with n > K (others get has = 0):
+ *   head[4] (premultiplied head composite), feat[9], target[4] (exact
+ *   premultiplied tail composite). */
+int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, double w0, double w1,
+                   double *head, double *feat, double *target, uint8_t *has) {
+    if (!(hot[3] > 0.0) || K < 1 || !(w1 > w0)) return ORC_EINVAL;
+    const orc_mesh *m = fr->m;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < fr->npix; ++s) {
+        int64_t n = fr->count[s];
+        int64_t i = fr->pix[s] % fr->W, j = fr->pix[s] / fr->W;
+        has[s] = n > K;
+        for (int a = 0; a < 4; ++a) head[4 * s + a] = target[4 * s + a] = 0.0;
+        for (int a = 0; a < 9; ++a) feat[9 * s + a] = 0.0;
+        if (n <= K) continue;
+        double Ch[3] = {0, 0, 0}, Ah = 0.0, Ct[3] = {0, 0, 0}, At = 0.0;
+        double sa = 0.0, sz[4] = {0, 0, 0, 0}, sc[3] = {0, 0, 0};
+        for (int64_t k = 0; k < n; ++k) {
+            uint64_t r = fr->rec[fr->off[s] + k];
+            uint32_t tri = (uint32_t)(r & 0xffffffffu);
+            frag f;
+            shade(fr, i, j, tri, hot, st, 0, &f, NULL);
+            if (k < K) {
+                double t = 1.0 - Ah;
+                for (int a = 0; a < 3; ++a) Ch[a] += t * f.c[a];
+                Ah += t * f.a;
+                continue;
+            }
+            double t = 1.0 - At;
+            for (int a = 0; a < 3; ++a) Ct[a] += t * f.c[a];
+            At += t * f.a;
+            /* proxy shading of the tail fragment */
+            int64_t fc = tri >> 1;
+            double ctr[3] = {0, 0, 0}, tbar = 0.0;
+            for (int c = 0; c < 4; ++c) {
+                int64_t v = m->face_v[4 * fc + c];
+                for (int a = 0; a < 3; ++a) ctr[a] += 0.25 * (double)m->pos_q[3 * v + a] / ORC_POS_SCALE;
+                tbar += 0.25 * m->t_v[v];
+            }
+            double dx = ctr[0] - hot[0], dy = ctr[1] - hot[1], dz = ctr[2] - hot[2];
+            double dist = sqrt(dx * dx + dy * dy + dz * dz) / hot[3];
+            if (dist > 1.0) dist = 1.0;
+            double al = (st[ST_A_LO] + (st[ST_A_HI] - st[ST_A_LO]) * tbar) * dist * dist * dist * dist;
+            double key = (double)(ORC_KMAX - (int64_t)(r >> 32));
+            double w = 1048576.0 / key;
+            double z = (w - w0) / (w1 - w0);
+            if (z < 0.0) z = 0.0;
+            if (z > 1.0) z = 1.0;
+            sa += al;
+            double zp = 1.0;
+            for (int p = 0; p < 4; ++p) { zp *= z; sz[p] += al * zp; }
+            for (int a = 0; a < 3; ++a) sc[a] += al * (st[ST_TF_LO + a] + (st[ST_TF_HI + a] - st[ST_TF_LO + a]) * tbar);
+        }
+        for (int a = 0; a < 3; ++a) { head[4 * s + a] = Ch[a]; target[4 * s + a] = Ct[a]; }
+        head[4 * s + 3] = Ah;
+        target[4 * s + 3] = At;
+        double *F = feat + 9 * s;
+        F[0] = log1p((double)(n - K));
+        F[1] = sa;
+        for (int p = 0; p < 4; ++p) F[2 + p] = sa > 0.0 ? sz[p] / sa : 0.0;
+        for (int a = 0; a < 3; ++a) F[6 + a] = sa > 0.0 ? sc[a] / sa : 0.0;
+    }
+    return ORC_OK;
+}
