@@ -191,8 +191,10 @@ hexfc_status hexfc_set_tuning(hexfc_ctx *ctx, int tile_w, int tile_h, int t_sort
 /* Statistics of the last build/render (host copy, no synchronisation):
  * out[0] bin entries, out[1] fragments, out[2] screen passes, out[8..15]
  * pixels per length class (0: n <= t_sort; 1..6: n <= 64, 128, 256, 512,
- * 1024, 2048; 7: longer), out[16..23] fragments per length class.
- * n = number of entries wanted (<= 24). */
+ * 1024, 2048; 7: longer), out[16..23] fragments per length class,
+ * out[24..31] pixels per class that the last hexfc_resolve_learned sent to
+ * the exact fallback (current once hexfc_batch_status has synchronised the
+ * statistics).  n = number of entries wanted (<= 32). */
 hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n);
 
 /* Per-launch timing with HIP events recorded on the launch stream (off by
@@ -200,8 +202,9 @@ hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n);
  * accumulated milliseconds and launch counts per kernel and resets them.
  * Kernel index: 0 transform, 1 triangle binning (count + tile scan),
  * 2 bin scatter, 3 coverage count, 4 pixel scan, 5 length classes, 6 pass
- * plan, 7 list fill, 8 + c resolve of length class c (c = 0..6).
- * n = number of entries wanted (<= 16). */
+ * plan, 7 list fill, 8 + c resolve of length class c (c = 0..6), 16 learned
+ * tail: head and features, 17 learned tail: network and compose, 18 learned
+ * tail: exact fallback.  n = number of entries wanted (<= 19). */
 hexfc_status hexfc_set_profiling(hexfc_ctx *ctx, int enable);
 hexfc_status hexfc_get_kernel_times(hexfc_ctx *ctx, double *ms_out, uint64_t *launches_out, int n);
 
@@ -215,6 +218,86 @@ hexfc_status hexfc_get_total_fragments(hexfc_ctx *ctx, uint64_t *out);
  * Errors: ESTATE (no lists). */
 hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uint64_t *off_out,
                                        uint64_t *rec_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned tail compositor.  Long per-pixel lists are resolved as an exact
+ * head (the first K fragments in depth order, shaded by Eq. 1-4 and blended
+ * front to back as in Section 3) plus a tail predicted by a small MLP from 9
+ * features of the remaining n - K fragments.  This follows the paper's
+ * future-work direction of approximating order-independent transparency
+ * (Section 7); it is not part of the paper's method, whose exact resolve
+ * (hexfc_resolve) stays the reference and the fallback.
+ *
+ * Tail features of a pixel (fragments i = K+1..n in depth order), with the
+ * proxy opacity a_i = alpha_TF(tbar_i) * min(|c_i - h| / r, 1)^4 and colour
+ * C_i = rgb_TF(tbar_i) of fragment i's face (c_i = centre of the face's
+ * dequantised corners, tbar_i = mean corner importance; h, r = hotspot) and
+ * the normalised view depth z_i = clamp((w_i - w0) / (w1 - w0), 0, 1)
+ * (w_i = 2^20 / depth key, [w0, w1] = clip-w range of the mesh bbox corners
+ * under the float camera matrix):
+ *   f0 = log1p(n - K), f1 = sum a_i, f2..f5 = sum a_i z_i^k / sum a_i
+ *   (k = 1..4), f6..f8 = sum a_i C_i / sum a_i (0 where sum a_i = 0).
+ *
+ * Network parameters: FP32 device vector of hexfc_mlp_param_count() = 5143
+ * floats, in this order: mu[9], inv_sigma[9] (input standardisation,
+ * x' = (x - mu) * inv_sigma; not trained), W1[9][64], b1[64], W2[64][64],
+ * b2[64], W3[64][5], b3[5] (row-major [in][out]); h1 = gelu(x' W1 + b1),
+ * h2 = gelu(h1 W2 + b2), y = h2 W3 + b3 with the tanh form of GELU.  y[0..3]
+ * is the tail's premultiplied RGBA, y[4] a confidence logit.  The kernels
+ * round weights and activations to BF16 for the matrix cores and accumulate
+ * in FP32; master weights and gradients are FP32.
+ * ---------------------------------------------------------------------- */
+
+/* Learned resolve of the lists of the last hexfc_build_fragment_lists (one
+ * view).  Lists of at most t_sort fragments (length class 0) and lists of at
+ * most K fragments are resolved exactly; for the others the exact head is
+ * composed with the predicted tail (clamped to [0, 1]) when
+ * sigmoid(y[4]) >= conf_min, else the pixel is resolved exactly (fallback).
+ *   params      device float[5143] (see above)
+ *   K           head length, 1..64
+ *   conf_min    confidence threshold in [0, 1); 0 accepts every prediction
+ *   rgba_out    device float [H][W][4] (as hexfc_resolve)
+ *   mask_out    device uint8 [H][W] or NULL: 1 = exact, 0 = learned tail
+ * Errors: ESTATE (no single-view lists), ERANGE (K, conf_min), EINVAL,
+ * EOVERFLOW (a list longer than 2048). */
+hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                   const float *params, int K, float conf_min, float *rgba_out,
+                                   uint8_t *mask_out, void *stream);
+
+/* Training and evaluation data of the learned resolve for the lists of the
+ * last hexfc_build_fragment_lists: one row per pixel of the long-list classes
+ * (n > t_sort), the rows hexfc_resolve_learned feeds to the network.
+ *   head_out    device float [cap][4] exact composite of the first K fragments
+ *   feat_out    device float [cap][9] tail features (above)
+ *   target_out  device float [cap][4] or NULL: exact composite of the tail
+ *               (fragments K+1..n shaded by Eq. 1-4, blended front to back)
+ *   pix_out     device uint32 [cap] pixel index y * W + x
+ *   rows_out    host: number of rows (all outputs NULL: size query only)
+ * Errors: ESTATE, ERANGE (K), EOVERFLOW (cap < rows). */
+hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style, int K,
+                                    float *head_out, float *feat_out, float *target_out, uint32_t *pix_out,
+                                    int64_t cap, int64_t *rows_out, void *stream);
+
+/* Network kernels on caller device buffers (no context; the current HIP
+ * device; status only, no error text).  n rows, row-major.
+ * forward:  y[n][5] = MLP(x[n][9]).
+ * loss:     per row, (1/4) sum_c (y_c - t_c)^2 + 0.1 * BCE(sigmoid(y_4), l),
+ *           l = 1 if max_c |y_c - t_c| < 2e-3 else 0 (target t[n][4]);
+ *           *loss_sum += sum over rows; dy[n][5] = d(mean loss)/dy.
+ * backward: grad[5143] += d(sum dy * y)/d params (entries 0..17 untouched);
+ *           the caller zeroes grad.
+ * adam:     one Adam step (step counts from 1, bias-corrected) on entries
+ *           18..5142 of params with moments m, v (each float[5143]).
+ * Errors: EINVAL (null pointer with n > 0, n < 0), ERANGE (Adam constants),
+ * EDEVICE (launch failure). */
+int64_t hexfc_mlp_param_count(void);
+hexfc_status hexfc_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream);
+hexfc_status hexfc_mlp_loss(const float *y, const float *target, int64_t n, float *dy, float *loss_sum,
+                            void *stream);
+hexfc_status hexfc_mlp_backward(const float *params, const float *x, const float *dy, int64_t n, float *grad,
+                                void *stream);
+hexfc_status hexfc_mlp_adam_step(float *params, float *m, float *v, const float *grad, float lr, float beta1,
+                                 float beta2, float eps, int step, void *stream);
 
 const char *hexfc_status_string(hexfc_status s);
 const char *hexfc_last_error(const hexfc_ctx *ctx);

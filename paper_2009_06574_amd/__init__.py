@@ -25,7 +25,8 @@ ABI_SYMBOLS = (
     "hexfc_build_fragment_lists", "hexfc_resolve", "hexfc_render_frame", "hexfc_set_tuning",
     "hexfc_get_frame_stats", "hexfc_get_total_fragments", "hexfc_export_sorted_lists",
     "hexfc_set_profiling", "hexfc_get_kernel_times", "hexfc_render_batch", "hexfc_batch_status",
-    "hexfc_autotune",
+    "hexfc_autotune", "hexfc_resolve_learned", "hexfc_learned_features", "hexfc_mlp_param_count",
+    "hexfc_mlp_forward", "hexfc_mlp_loss", "hexfc_mlp_backward", "hexfc_mlp_adam_step",
     "hexfc_status_string", "hexfc_last_error",
 )
 
@@ -81,6 +82,15 @@ def load():
         "hexfc_render_batch": ([P, ct.c_int, P, P, P, P, P], st),
         "hexfc_batch_status": ([P, P, P, P], st),
         "hexfc_autotune": ([P, ct.c_int, P, P, P, P, ct.c_char_p, P, P], st),
+        "hexfc_resolve_learned": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), P, ct.c_int, ct.c_float, P, P, P],
+                                  st),
+        "hexfc_learned_features": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), ct.c_int, P, P, P, P, i64, P, P],
+                                   st),
+        "hexfc_mlp_param_count": ([], i64),
+        "hexfc_mlp_forward": ([P, P, i64, P, P], st),
+        "hexfc_mlp_loss": ([P, P, i64, P, P, P], st),
+        "hexfc_mlp_backward": ([P, P, P, i64, P, P], st),
+        "hexfc_mlp_adam_step": ([P, P, P, P, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_int, P], st),
         "hexfc_status_string": ([st], ct.c_char_p),
         "hexfc_last_error": ([P], ct.c_char_p),
     }
@@ -261,14 +271,51 @@ class Renderer:
         return int(v.value)
 
     def frame_stats(self) -> dict:
-        a = (ct.c_uint64 * 24)()
-        self._check(self.lib.hexfc_get_frame_stats(self.ctx, a, 24))
+        a = (ct.c_uint64 * 32)()
+        self._check(self.lib.hexfc_get_frame_stats(self.ctx, a, 32))
         return dict(bins=int(a[0]), fragments=int(a[1]), passes=int(a[2]),
                     classes=[int(a[8 + i]) for i in range(8)],
-                    class_fragments=[int(a[16 + i]) for i in range(8)])
+                    class_fragments=[int(a[16 + i]) for i in range(8)],
+                    fallback=[int(a[24 + i]) for i in range(8)])
 
     KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill") + tuple(
-        f"resolve_c{c}" for c in range(8))
+        f"resolve_c{c}" for c in range(8)) + ("tail_features", "mlp_apply", "fallback")
+
+    # ------------------------------------------------------------ learned tail
+    def learned_features(self, hot, style, K: int = 8, with_target: bool = False) -> dict:
+        """Rows of the learned resolve for the last built lists: head [r,4], feat [r,9],
+        target [r,4] (exact tail, if asked) and pix [r] (y*W+x, int32)."""
+        rows = ct.c_int64()
+        hs, ss = hotspot_struct(hot), style_struct(style)
+        self._check(self.lib.hexfc_learned_features(self.ctx, ct.byref(hs), ct.byref(ss), int(K), None, None, None,
+                                                    None, 0, ct.byref(rows), self._stream()))
+        r = int(rows.value)
+        t = self.torch
+        out = dict(head=t.empty((max(r, 1), 4), dtype=t.float32, device=self.device),
+                   feat=t.empty((max(r, 1), 9), dtype=t.float32, device=self.device),
+                   target=t.empty((max(r, 1), 4), dtype=t.float32, device=self.device) if with_target else None,
+                   pix=t.empty(max(r, 1), dtype=t.int32, device=self.device))
+        self._check(self.lib.hexfc_learned_features(self.ctx, ct.byref(hs), ct.byref(ss), int(K), _ptr(out["head"]),
+                                                    _ptr(out["feat"]), _ptr(out["target"]), _ptr(out["pix"]),
+                                                    max(r, 1), ct.byref(rows), self._stream()))
+        return {k: (None if v is None else v[:r]) for k, v in out.items()}
+
+    def resolve_learned(self, hot, style, params, K: int = 8, conf_min: float = 0.5, out=None, mask=True):
+        """Learned-tail resolve of the last built lists: (rgba [H,W,4], mask [H,W] uint8 or None)."""
+        t = self.torch
+        if out is None:
+            out = t.empty((self.H, self.W, 4), dtype=t.float32, device=self.device)
+        m = None
+        if mask is True:
+            m = t.empty((self.H, self.W), dtype=t.uint8, device=self.device)
+        elif mask is not None and mask is not False:
+            m = mask
+        params = _f32(params, self.device)
+        self._check(self.lib.hexfc_resolve_learned(self.ctx, ct.byref(hotspot_struct(hot)),
+                                                   ct.byref(style_struct(style)), _ptr(params), int(K),
+                                                   float(conf_min), _ptr(out), _ptr(m), self._stream()))
+        return out, m
+
 
     def set_profiling(self, on: bool = True):
         self._check(self.lib.hexfc_set_profiling(self.ctx, 1 if on else 0))
@@ -279,3 +326,80 @@ class Renderer:
         n = (ct.c_uint64 * 16)()
         self._check(self.lib.hexfc_get_kernel_times(self.ctx, ms, n, 16))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS) if n[i]}
+
+
+# ---------------------------------------------------------------- learned-tail network kernels
+def _f32(t, device=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float32))
+    if device is not None and t.device != torch.device(device):
+        t = t.to(device)
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        t = t.to(torch.float32).contiguous()
+    if t.device.type != "cuda":
+        raise ValueError("learned-tail kernels need CUDA (HIP) tensors")
+    return t
+
+
+def _status(rc):
+    if rc != 0:
+        raise HexfcError(rc, "learned-tail kernel call failed")
+
+
+def _cur_stream(t):
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_param_count() -> int:
+    return int(load().hexfc_mlp_param_count())
+
+
+def mlp_forward(params, x, y=None):
+    """y [n,5] = MLP(x [n,9]) on the GPU."""
+    import torch
+    lib = load()
+    x = _f32(x)
+    params = _f32(params, x.device)
+    n = x.shape[0]
+    if y is None:
+        y = torch.empty((n, 5), dtype=torch.float32, device=x.device)
+    _status(lib.hexfc_mlp_forward(_ptr(params), _ptr(x), n, _ptr(y), _cur_stream(x)))
+    return y
+
+
+def mlp_loss(y, target, dy=None, loss_sum=None):
+    """(dy [n,5], loss_sum [1]): loss_sum accumulates the per-row losses."""
+    import torch
+    lib = load()
+    y, target = _f32(y), _f32(target)
+    n = y.shape[0]
+    if dy is None:
+        dy = torch.empty((n, 5), dtype=torch.float32, device=y.device)
+    if loss_sum is None:
+        loss_sum = torch.zeros(1, dtype=torch.float32, device=y.device)
+    _status(lib.hexfc_mlp_loss(_ptr(y), _ptr(target), n, _ptr(dy), _ptr(loss_sum), _cur_stream(y)))
+    return dy, loss_sum
+
+
+def mlp_backward(params, x, dy, grad=None):
+    """grad += d(sum dy*y)/d params (a zeroed gradient is allocated if none is given)."""
+    import torch
+    lib = load()
+    x, dy = _f32(x), _f32(dy)
+    params = _f32(params, x.device)
+    if grad is None:
+        grad = torch.zeros(mlp_param_count(), dtype=torch.float32, device=x.device)
+    _status(lib.hexfc_mlp_backward(_ptr(params), _ptr(x), _ptr(dy), x.shape[0], _ptr(grad), _cur_stream(x)))
+    return grad
+
+
+def mlp_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on float32 CUDA tensors params, m, v."""
+    lib = load()
+    for t in (params, m, v, grad):
+        if t.dtype.__repr__() != "torch.float32" or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError("params, m, v and grad must be contiguous float32 CUDA tensors")
+    _status(lib.hexfc_mlp_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), float(lr), float(beta1),
+                                    float(beta2), float(eps), int(step), _cur_stream(params)))

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhexfc.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "frame.hip", "geom.hip", "resolve.hip"]
+SOURCES = ["api.hip", "frame.hip", "geom.hip", "resolve.hip", "learned.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(os.path.dirname(HERE), "include")]

@@ -267,12 +267,34 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
     HIPCHK(ctx, hipMemcpy(ctx->posq.p, posq4.data(), sizeof(int32_t) * 4 * V, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ctx->vert0.p, vrec.data(), sizeof(VertRec) * V, hipMemcpyHostToDevice));
     HIPCHK(ctx, ctx->face_c.ensure(sizeof(int4) * std::max<int64_t>(F, 1)));
+    HIPCHK(ctx, ctx->face_px.ensure(sizeof(float4) * std::max<int64_t>(F, 1)));
     if (F) {
         std::vector<int4> fc(F);
-        for (int64_t f = 0; f < F; ++f) fc[f] = frec[f].c;
+        std::vector<float4> px(F);  // face centre and mean corner importance (learned-tail proxy)
+        for (int64_t f = 0; f < F; ++f) {
+            fc[f] = frec[f].c;
+            const int cv[4] = {fc[f].x, fc[f].y, fc[f].z, fc[f].w};
+            double ctr[3] = {0, 0, 0}, tbar = 0.0;
+            for (int k = 0; k < 4; ++k) {
+                for (int a = 0; a < 3; ++a) ctr[a] += 0.25 * (q[3 * (int64_t)cv[k] + a] / 65536.0);
+                tbar += 0.25 * tv[cv[k]];
+            }
+            px[f] = make_float4((float)ctr[0], (float)ctr[1], (float)ctr[2], (float)tbar);
+        }
         HIPCHK(ctx, hipMemcpy(ctx->face.p, frec.data(), sizeof(FaceRec) * F, hipMemcpyHostToDevice));
         HIPCHK(ctx, hipMemcpy(ctx->face_c.p, fc.data(), sizeof(int4) * F, hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(ctx->face_px.p, px.data(), sizeof(float4) * F, hipMemcpyHostToDevice));
     }
+    for (int a = 0; a < 3; ++a) {  // bbox of the dequantised positions
+        ctx->bbox_lo[a] = 1e300;
+        ctx->bbox_hi[a] = -1e300;
+    }
+    for (int64_t v = 0; v < V; ++v)
+        for (int a = 0; a < 3; ++a) {
+            const double x = q[3 * v + a] / 65536.0;
+            ctx->bbox_lo[a] = std::min(ctx->bbox_lo[a], x);
+            ctx->bbox_hi[a] = std::max(ctx->bbox_hi[a], x);
+        }
     ctx->V = V;
     ctx->C = C;
     ctx->F = F;

@@ -60,7 +60,8 @@ struct hexfc_ctx {
     std::string err;
     // mesh
     int64_t V = 0, C = 0, F = 0;
-    hexfc::DevBuf posq, vert0, face, face_c;
+    hexfc::DevBuf posq, vert0, face, face_c, face_px;
+    double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
     // tuning
     int tw = 8, th = 8, t_sort = 16;
     // workspace (caller-owned)
@@ -69,6 +70,8 @@ struct hexfc_ctx {
     // per-frame scratch, sized for `nv_cap` views
     hexfc::DevBuf vert_b, vscr, views, tile_cnt, tile_fill, tile_off, bins, masks, count, off, scan_tmp, cls, stats;
     hexfc::DevBuf count_rm_tmp;
+    // learned tail: per-row head, features and pixel ids, fallback lists
+    hexfc::DevBuf l_head, l_feat, l_pix, l_fb;
     int vert_b_views = 0;  // views whose world part is initialised in vert_b
     uint64_t bin_cap = 0;
     int64_t cls_cap = 0;

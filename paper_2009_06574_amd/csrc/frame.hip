@@ -54,6 +54,24 @@ void shade_params(ShadeParams &p, const hexfc_hotspot *hot, const hexfc_style *s
     p.a_hi = sty->tf_a_hi;
 }
 
+// View-depth range [w0, w1] of the mesh bbox: clip w (row 3 of the float
+// camera matrix) at its 8 corners.  Normalises the learned tail's depth feature.
+void depth_range(const hexfc_ctx *ctx, const hexfc_camera *cam, ViewParams &vp) {
+    double lo = 1e300, hi = -1e300;
+    for (int c = 0; c < 8; ++c) {
+        const double x = (c & 1) ? ctx->bbox_hi[0] : ctx->bbox_lo[0];
+        const double y = (c & 2) ? ctx->bbox_hi[1] : ctx->bbox_lo[1];
+        const double z = (c & 4) ? ctx->bbox_hi[2] : ctx->bbox_lo[2];
+        const float *m = cam->view_proj + 12;
+        const double w = (double)m[0] * x + (double)m[1] * y + (double)m[2] * z + (double)m[3];
+        lo = std::min(lo, w);
+        hi = std::max(hi, w);
+    }
+    if (!(hi > lo)) hi = lo + 1.0;
+    vp.w0 = (float)lo;
+    vp.w1 = (float)hi;
+}
+
 Tiling make_tiling(const hexfc_ctx *ctx, int W, int H) {
     Tiling tl;
     tl.W = W;
@@ -191,6 +209,7 @@ hexfc_status prepare(hexfc_ctx *ctx, int nv, const hexfc_camera *cams, hipStream
         TRY(check_camera(ctx, &cams[v], ctx->h_views[v].M));
         if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
             FAIL(ctx, HEXFC_EINVAL, "all views of a batch must have the same viewport");
+        depth_range(ctx, &cams[v], ctx->h_views[v]);
     }
     const Tiling tl = make_tiling(ctx, cams[0].width, cams[0].height);
     TRY(ensure_frame_buffers(ctx, nv, tl));
@@ -220,6 +239,7 @@ ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba) {
     a.mesh.face = ctx->face.as<FaceRec>();
     a.mesh.face_c = ctx->face_c.as<int4>();
     a.mesh.vscr = ctx->vscr.as<int4>();
+    a.mesh.face_px = ctx->face_px.as<float4>();
     a.mesh.V = ctx->V;
     a.mesh.F = ctx->F;
     a.views = ctx->views.as<ViewParams>();
@@ -352,6 +372,7 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
             FAIL(ctx, HEXFC_EINVAL, "all views of a batch must have the same viewport");
         TRY(check_shading(ctx, &hots[v], &styles[v], rgba_out));
         shade_params(ctx->h_views[v].sp, &hots[v], &styles[v]);
+        depth_range(ctx, &cams[v], ctx->h_views[v]);
     }
     ctx->lists_valid = false;
     BatchGraph &g = ctx->bg;
@@ -461,6 +482,111 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
     a.sorted_out = rec_out;
     a.off_rm = off_out;
     launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
+    HIPCHK(ctx, hipGetLastError());
+    return HEXFC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned tail
+namespace {
+
+// Rows of the learned resolve: pixels of the long-list classes 1..6.
+int64_t learned_rows(const hexfc_ctx *ctx) {
+    int64_t n = 0;
+    for (int c = 1; c < NCLASS - 1; ++c) n += (int64_t)ctx->last_stats[ST_CLASS + c];
+    return n;
+}
+
+hexfc_status learned_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style, int K) {
+    if (!ctx->lists_valid || ctx->nv != 1) FAIL(ctx, HEXFC_ESTATE, "no single-view fragment lists built");
+    if (!hot || !style) FAIL(ctx, HEXFC_EINVAL, "null hotspot or style");
+    if (!(hot->radius > 0.f) || !std::isfinite(hot->radius)) FAIL(ctx, HEXFC_EINVAL, "hotspot radius must be > 0");
+    if (K < 1 || K > 64) FAIL(ctx, HEXFC_ERANGE, "K must be in [1, 64]");
+    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
+        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
+    return HEXFC_OK;
+}
+
+// Head composites and tail features of every long-list pixel, rows in class order.
+void enqueue_tail_features(hexfc_ctx *ctx, const ResolveArgs &a, int K, float *head, float *feat, float *target,
+                           uint32_t *pix, bool rowmajor, hipStream_t s) {
+    ScopedTimer tm(ctx, s, KID_TAIL);
+    int64_t base = 0;
+    for (int c = 1; c < NCLASS - 1; ++c) {
+        const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
+        launch_tail_features(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap, nc, K, a, head, feat, target, pix,
+                             rowmajor, base, s);
+        base += nc;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style, int K,
+                                    float *head_out, float *feat_out, float *target_out, uint32_t *pix_out,
+                                    int64_t cap, int64_t *rows_out, void *stream) {
+    if (!ctx || !rows_out) return HEXFC_EINVAL;
+    TRY(learned_checks(ctx, hot, style, K));
+    const int64_t rows = learned_rows(ctx);
+    *rows_out = rows;
+    if (!head_out && !feat_out && !target_out && !pix_out) return HEXFC_OK;  // size query
+    if (!head_out || !feat_out || !pix_out) FAIL(ctx, HEXFC_EINVAL, "null output");
+    if (cap < rows) FAIL(ctx, HEXFC_EOVERFLOW, "%lld rows exceed the output capacity %lld", (long long)rows,
+                         (long long)cap);
+    TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    shade_params(ctx->h_views[0].sp, hot, style);
+    TRY(upload_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, nullptr);
+    enqueue_tail_features(ctx, a, K, head_out, feat_out, target_out, pix_out, true, s);
+    HIPCHK(ctx, hipGetLastError());
+    return HEXFC_OK;
+}
+
+hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                   const float *params, int K, float conf_min, float *rgba_out, uint8_t *mask_out,
+                                   void *stream) {
+    if (!ctx) return HEXFC_EINVAL;
+    TRY(learned_checks(ctx, hot, style, K));
+    if (!params || !rgba_out) FAIL(ctx, HEXFC_EINVAL, "null parameters or output");
+    if (!(conf_min >= 0.f && conf_min < 1.f)) FAIL(ctx, HEXFC_ERANGE, "conf_min must be in [0, 1)");
+    TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const Tiling &tl = ctx->tl;
+    const int64_t rows = learned_rows(ctx);
+    TRY(grow(ctx, ctx->l_head, sizeof(float4) * std::max<int64_t>(rows, 1)));
+    TRY(grow(ctx, ctx->l_feat, sizeof(float) * NFEAT * std::max<int64_t>(rows, 1)));
+    TRY(grow(ctx, ctx->l_pix, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
+    TRY(grow(ctx, ctx->l_fb, sizeof(uint32_t) * NCLASS * std::max<int64_t>(ctx->cls_cap, 1)));
+    shade_params(ctx->h_views[0].sp, hot, style);
+    TRY(upload_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, rgba_out);
+    uint64_t *stats = ctx->stats.as<uint64_t>();
+    if (mask_out) launch_fill_u8(mask_out, (int64_t)tl.W * tl.H, 1, s);
+    launch_zero_u64(stats + ST_FB, NCLASS, s);
+    if (ctx->last_stats[ST_CLASS]) {  // short lists: exact
+        ScopedTimer tm(ctx, s, KID_RESOLVE0);
+        launch_resolve_class(0, ctx->cls.as<uint32_t>(), (uint32_t)ctx->last_stats[ST_CLASS], nullptr, ctx->t_sort, a,
+                             s);
+    }
+    if (rows) {
+        float *head = ctx->l_head.as<float>(), *feat = ctx->l_feat.as<float>();
+        uint32_t *pix = ctx->l_pix.as<uint32_t>(), *fb = ctx->l_fb.as<uint32_t>();
+        enqueue_tail_features(ctx, a, K, head, feat, nullptr, pix, false, s);
+        {
+            ScopedTimer tm(ctx, s, KID_MLP);
+            launch_mlp_apply(params, feat, head, pix, rows, a, ctx->t_sort, K, conf_min, fb, ctx->cls_cap, stats,
+                             mask_out, s);
+        }
+        ScopedTimer tm(ctx, s, KID_FALLBACK);
+        for (int c = 1; c < NCLASS - 1; ++c) {
+            if (!ctx->last_stats[ST_CLASS + c]) continue;
+            launch_resolve_class(c, fb + (int64_t)c * ctx->cls_cap, 0, stats + ST_FB + c, ctx->t_sort, a, s);
+        }
+    }
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }

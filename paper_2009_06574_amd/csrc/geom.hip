@@ -471,17 +471,6 @@ void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, ui
 }
 
 // ------------------------------------------------------------------ length classes
-__device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
-    if (n <= (uint32_t)t_sort) return 0;
-    if (n <= 64) return 1;
-    if (n <= 128) return 2;
-    if (n <= 256) return 3;
-    if (n <= 512) return 4;
-    if (n <= 1024) return 5;
-    if (n <= 2048) return 6;
-    return 7;
-}
-
 __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t p1,
                                                   const uint32_t *__restrict__ count, int t_sort,
                                                   uint32_t *__restrict__ lists, int64_t cap,

@@ -33,15 +33,19 @@ enum StatSlot {
     ST_PLAN_ERR = 3,  // a single tile exceeds the workspace
     ST_CLASS = 8,     // NCLASS class sizes (pixels)
     ST_CLASSF = 16,   // NCLASS class sizes (fragments)
-    ST_PASS = 24,     // MAX_PASSES + 1 tile boundaries
-    ST_COUNT = 24 + MAX_PASSES + 1
+    ST_FB = 24,       // NCLASS pixels sent back to the exact resolve by the learned one
+    ST_PASS = 32,     // MAX_PASSES + 1 tile boundaries
+    ST_COUNT = 32 + MAX_PASSES + 1
 };
 
 // kernels timed by the optional per-launch HIP-event profiler
 enum KernelId {
     KID_TRANSFORM = 0, KID_BIN_COUNT, KID_BIN_SCATTER, KID_COUNT, KID_SCAN, KID_CLASSIFY, KID_PLAN, KID_FILL,
     KID_RESOLVE0,  // + length class
-    KID_COUNT_ = KID_RESOLVE0 + NCLASS
+    KID_TAIL = KID_RESOLVE0 + NCLASS,  // learned resolve: head and tail features
+    KID_MLP,                           // learned resolve: network and compose
+    KID_FALLBACK,                      // learned resolve: exact fallback
+    KID_COUNT_
 };
 
 struct Mat3q { long long m[3][4]; };  // rows x, y, w of M_q
@@ -74,6 +78,8 @@ struct ShadeParams {
 struct ViewParams {
     Mat3q M;
     ShadeParams sp;
+    float w0, w1;  // view-depth range of the mesh bbox (learned-tail depth feature)
+    float pad0, pad1;
 };
 
 struct Tiling {
@@ -87,6 +93,7 @@ struct DevMesh {
     const FaceRec *face;   // [F]
     const int4 *face_c;    // [F] corner ids alone (dense, for the rasteriser)
     const int4 *vscr;      // [NV*V] screen part alone (dense, for the rasteriser)
+    const float4 *face_px; // [F] face centre (xyz) and mean corner importance: learned-tail proxy
     int64_t V, F;
 };
 
@@ -95,6 +102,35 @@ struct DevMesh {
 __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
     const uint32_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
     return x * q + min(x, r) + i;
+}
+
+// Global pixel id -> view and pixel coordinates.
+struct PixelRef {
+    int64_t view;
+    int x, y;
+};
+__device__ __forceinline__ PixelRef pixel_ref(const Tiling &tl, uint32_t gp) {
+    const int TP = tl.TW * tl.TH;
+    const int64_t pt = (int64_t)tl.ntiles * TP;
+    PixelRef r;
+    r.view = gp / pt;
+    const int64_t p = gp - r.view * pt;
+    const int tile = (int)(p / TP), l = (int)(p % TP);
+    r.x = (tile % tl.ntx) * tl.TW + l % tl.TW;
+    r.y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+    return r;
+}
+
+// Length class of a list of n fragments (see NCLASS).
+__device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
+    if (n <= (uint32_t)t_sort) return 0;
+    if (n <= 64) return 1;
+    if (n <= 128) return 2;
+    if (n <= 256) return 3;
+    if (n <= 512) return 4;
+    if (n <= 1024) return 5;
+    if (n <= 2048) return 6;
+    return 7;
 }
 
 // ---------------------------------------------------------------- launchers (geom.hip)
@@ -143,5 +179,35 @@ struct ResolveArgs {
 // persistent grid that reads the class size from device memory (graph replay).
 void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
                           const ResolveArgs &a, hipStream_t s);
+
+// Learned tail (resolve.hip): for the pixels of long-list class cls, the exact
+// composite of the first K sorted fragments (head[4]), 9 tail features and,
+// when target != nullptr, the exact composite of the tail (target[4]); row j
+// of the outputs is pixel pix_list[j], stored at out_base + j.
+constexpr int NFEAT = 9;
+// pix_out receives the global tile-major pixel id, or with rowmajor the
+// image index (view * H + y) * W + x.
+void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a,
+                          float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
+                          int64_t out_base, hipStream_t s);
+
+// Learned tail network (learned.hip).  Parameters: FP32 vector of MLP_PARAMS
+// floats: mu[9], inv_sigma[9], W1[9][64], b1[64], W2[64][64], b2[64],
+// W3[64][5], b3[5]; outputs y[5] = tail RGBA + confidence logit.
+constexpr int MLP_PARAMS = 18 + 9 * 64 + 64 + 64 * 64 + 64 + 64 * 5 + 5;
+void launch_mlp_forward(const float *params, const float *X, int64_t n, float *Y, hipStream_t s);
+void launch_mlp_loss(const float *Y, const float *T, int64_t n, float *dY, float *loss_sum, hipStream_t s);
+void launch_mlp_backward(const float *params, const float *X, const float *dY, int64_t n, float *grad,
+                         hipStream_t s);
+void launch_adam(float *w, float *m, float *v, const float *g, int count, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t s);
+// Apply the network to n learned pixels and compose with their heads; pixels
+// with more than K fragments whose confidence is below conf_min are appended
+// to the per-class fallback lists (fb + c*fb_cap, sizes in stats[ST_FB + c]);
+// mask (nullable) gets 0 where the learned tail was used.
+void launch_mlp_apply(const float *params, const float *feat, const float *head, const uint32_t *pix, int64_t n,
+                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, int64_t fb_cap,
+                      uint64_t *stats, uint8_t *mask, hipStream_t s);
+void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 }  // namespace hexfc

@@ -118,23 +118,6 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
     return o;
 }
 
-// Global pixel id -> view and pixel coordinates.
-struct PixelRef {
-    int64_t view;
-    int x, y;
-};
-__device__ __forceinline__ PixelRef pixel_ref(const Tiling &tl, uint32_t gp) {
-    const int TP = tl.TW * tl.TH;
-    const int64_t pt = (int64_t)tl.ntiles * TP;
-    PixelRef r;
-    r.view = gp / pt;
-    const int64_t p = gp - r.view * pt;
-    const int tile = (int)(p / TP), l = (int)(p % TP);
-    r.x = (tile % tl.ntx) * tl.TW + l % tl.TW;
-    r.y = (tile / tl.ntx) * tl.TH + l / tl.TW;
-    return r;
-}
-
 constexpr float T_EPS = 9.5367431640625e-07f;  // 2^-20: stop once 1 - A is below it
 
 // ------------------------------------------------------------------ short lists
@@ -313,6 +296,152 @@ void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, cons
         case 6: k_resolve_long<32><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
         default: break;
     }
+}
+
+// ------------------------------------------------------------------ learned tail: head and tail features
+// Wave per pixel, as the long-list resolve: sort, then the first K positions
+// are shaded exactly and composited (head); the tail positions get the proxy
+// shading (face centre distance to the hotspot, mean corner importance) whose
+// sums make the 9 features; with TRAIN the tail is also shaded exactly and
+// composited (the regression target).
+__device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, float &A, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o), qa = __shfl_down(A, o);
+        if ((lane & (2 * o - 1)) == 0) {
+            const float T = 1.f - A;
+            C0 += T * q0;
+            C1 += T * q1;
+            C2 += T * q2;
+            A += T * qa;
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int R, bool TRAIN>
+__global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restrict__ list, uint32_t npix, int K,
+                                                       ResolveArgs a, float *__restrict__ head,
+                                                       float *__restrict__ feat, float *__restrict__ target,
+                                                       uint32_t *__restrict__ pix_out, bool rowmajor,
+                                                       int64_t out_base) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (wave >= npix) return;
+    const uint32_t p = list[wave];
+    uint32_t n = min(a.count[p], (uint32_t)(64 * R));
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    if (first + n > a.rec_cap) n = 0;
+    const uint64_t *src = a.rec + first;
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        v[r] = e < n ? src[e] : ~0ull;
+    }
+    bitonic_sort<R>(v, lane);
+    const PixelRef pr = pixel_ref(a.tl, p);
+    const ViewParams &vp = a.views[pr.view];
+    const ShadeParams &sp = vp.sp;
+    const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    const float zs = 1.f / (vp.w1 - vp.w0);
+    float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;  // head composite
+    float T0 = 0.f, T1 = 0.f, T2 = 0.f, TA = 0.f;  // exact tail composite
+    float sa = 0.f, sz1 = 0.f, sz2 = 0.f, sz3 = 0.f, sz4 = 0.f, sc0 = 0.f, sc1 = 0.f, sc2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        if (e >= n) continue;
+        const uint32_t tri = (uint32_t)(v[r] & 0xffffffffu);
+        if ((int)e < K || TRAIN) {
+            const Frag fr = shade(a.mesh, vert, sp, tri, pr.x, pr.y);
+            if ((int)e < K) {
+                const float T = 1.f - HA;
+                H0 += T * fr.r;
+                H1 += T * fr.g;
+                H2 += T * fr.b;
+                HA += T * fr.a;
+            } else {
+                const float T = 1.f - TA;
+                T0 += T * fr.r;
+                T1 += T * fr.g;
+                T2 += T * fr.b;
+                TA += T * fr.a;
+            }
+        }
+        if ((int)e >= K) {
+            const float4 fp = a.mesh.face_px[tri >> 1];
+            const float dx = fp.x - sp.hc[0], dy = fp.y - sp.hc[1], dz = fp.z - sp.hc[2];
+            const float dist = fminf(sqrtf(dx * dx + dy * dy + dz * dz) * sp.inv_r, 1.f);
+            const float d2 = dist * dist;
+            const float al = (sp.a_lo + (sp.a_hi - sp.a_lo) * fp.w) * d2 * d2;
+            const float key = (float)(KMAX - (uint32_t)(v[r] >> 32));
+            const float z = fminf(fmaxf((1048576.f / key - vp.w0) * zs, 0.f), 1.f);
+            const float z2 = z * z;
+            sa += al;
+            sz1 += al * z;
+            sz2 += al * z2;
+            sz3 += al * z2 * z;
+            sz4 += al * z2 * z2;
+            sc0 += al * (sp.lo[0] + (sp.hi[0] - sp.lo[0]) * fp.w);
+            sc1 += al * (sp.lo[1] + (sp.hi[1] - sp.lo[1]) * fp.w);
+            sc2 += al * (sp.lo[2] + (sp.hi[2] - sp.lo[2]) * fp.w);
+        }
+    }
+    over_reduce(H0, H1, H2, HA, lane);
+    if (TRAIN) over_reduce(T0, T1, T2, TA, lane);
+    sa = wave_sum(sa);
+    sz1 = wave_sum(sz1);
+    sz2 = wave_sum(sz2);
+    sz3 = wave_sum(sz3);
+    sz4 = wave_sum(sz4);
+    sc0 = wave_sum(sc0);
+    sc1 = wave_sum(sc1);
+    sc2 = wave_sum(sc2);
+    if (lane == 0) {
+        const int64_t o = out_base + wave;
+        const float inv = sa > 0.f ? 1.f / sa : 0.f;
+        float *F = feat + o * NFEAT;
+        F[0] = log1pf((float)max((int)n - K, 0));
+        F[1] = sa;
+        F[2] = sz1 * inv;
+        F[3] = sz2 * inv;
+        F[4] = sz3 * inv;
+        F[5] = sz4 * inv;
+        F[6] = sc0 * inv;
+        F[7] = sc1 * inv;
+        F[8] = sc2 * inv;
+        reinterpret_cast<float4 *>(head)[o] = make_float4(H0, H1, H2, HA);
+        if (TRAIN) reinterpret_cast<float4 *>(target)[o] = make_float4(T0, T1, T2, TA);
+        pix_out[o] = rowmajor ? (uint32_t)((pr.view * a.tl.H + pr.y) * a.tl.W + pr.x) : p;
+    }
+}
+
+void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a, float *head,
+                          float *feat, float *target, uint32_t *pix_out, bool rowmajor, int64_t out_base,
+                          hipStream_t s) {
+    if (npix == 0) return;
+    dim3 g((npix + 3) / 4);
+#define TAIL(RV)                                                                                                     \
+    if (target)                                                                                                      \
+        k_tail_features<RV, true><<<g, 256, 0, s>>>(pix_list, npix, K, a, head, feat, target, pix_out, rowmajor, out_base);    \
+    else                                                                                                             \
+        k_tail_features<RV, false><<<g, 256, 0, s>>>(pix_list, npix, K, a, head, feat, target, pix_out, rowmajor, out_base);
+    switch (cls) {
+        case 1: TAIL(1); break;
+        case 2: TAIL(2); break;
+        case 3: TAIL(4); break;
+        case 4: TAIL(8); break;
+        case 5: TAIL(16); break;
+        case 6: TAIL(32); break;
+        default: break;
+    }
+#undef TAIL
 }
 
 }  // namespace hexfc
