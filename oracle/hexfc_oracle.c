@@ -710,8 +710,9 @@ int orc_num_threads(void) {
  *                   corners and tbar the mean corner importance;
  *   depth z = (w - w0) / (w1 - w0) clamped to [0,1], w = 2^20 / key the view
  *   depth of the fragment, [w0, w1] the view-depth range of the mesh bbox;
- *   features: log1p(n_tail), sum alpha~, sum alpha~ z^k / sum alpha~ (k=1..4),
- *   sum alpha~ colour~ / sum alpha~ (3).
+ *   features: log1p(n_tail), sum alpha~, sum alpha~ z^k / sum alpha~ (k=1,2),
+ *   the premultiplied RGBA of the proxies composited front to back in depth
+ *   order (4), and z of the first tail fragment.
  * Outputs per sample pixel with n > K (others get has = 0):
  *   head[4] (premultiplied head composite), feat[9], target[4] (exact
  *   premultiplied tail composite). */
@@ -728,7 +729,7 @@ int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, do
         for (int a = 0; a < 9; ++a) feat[9 * s + a] = 0.0;
         if (n <= K) continue;
         double Ch[3] = {0, 0, 0}, Ah = 0.0, Ct[3] = {0, 0, 0}, At = 0.0;
-        double sa = 0.0, sz[4] = {0, 0, 0, 0}, sc[3] = {0, 0, 0};
+        double sa = 0.0, sz[2] = {0, 0}, P[3] = {0, 0, 0}, PA = 0.0, zf = 0.0;
         for (int64_t k = 0; k < n; ++k) {
             uint64_t r = fr->rec[fr->off[s] + k];
             uint32_t tri = (uint32_t)(r & 0xffffffffu);
@@ -743,7 +744,8 @@ int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, do
             double t = 1.0 - At;
             for (int a = 0; a < 3; ++a) Ct[a] += t * f.c[a];
             At += t * f.a;
-            /* proxy shading of the tail fragment */
+            /* proxy shading of the tail fragment: its face's centre and mean
+               corner importance */
             int64_t fc = tri >> 1;
             double ctr[3] = {0, 0, 0}, tbar = 0.0;
             for (int c = 0; c < 4; ++c) {
@@ -760,10 +762,14 @@ int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, do
             double z = (w - w0) / (w1 - w0);
             if (z < 0.0) z = 0.0;
             if (z > 1.0) z = 1.0;
+            if (k == K) zf = z;
             sa += al;
-            double zp = 1.0;
-            for (int p = 0; p < 4; ++p) { zp *= z; sz[p] += al * zp; }
-            for (int a = 0; a < 3; ++a) sc[a] += al * (st[ST_TF_LO + a] + (st[ST_TF_HI + a] - st[ST_TF_LO + a]) * tbar);
+            sz[0] += al * z;
+            sz[1] += al * z * z;
+            /* front-to-back composite of the proxies */
+            double tp = 1.0 - PA;
+            for (int a = 0; a < 3; ++a) P[a] += tp * al * (st[ST_TF_LO + a] + (st[ST_TF_HI + a] - st[ST_TF_LO + a]) * tbar);
+            PA += tp * al;
         }
         for (int a = 0; a < 3; ++a) { head[4 * s + a] = Ch[a]; target[4 * s + a] = Ct[a]; }
         head[4 * s + 3] = Ah;
@@ -771,8 +777,11 @@ int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, do
         double *F = feat + 9 * s;
         F[0] = log1p((double)(n - K));
         F[1] = sa;
-        for (int p = 0; p < 4; ++p) F[2 + p] = sa > 0.0 ? sz[p] / sa : 0.0;
-        for (int a = 0; a < 3; ++a) F[6 + a] = sa > 0.0 ? sc[a] / sa : 0.0;
+        F[2] = sa > 0.0 ? sz[0] / sa : 0.0;
+        F[3] = sa > 0.0 ? sz[1] / sa : 0.0;
+        for (int a = 0; a < 3; ++a) F[4 + a] = P[a];
+        F[7] = PA;
+        F[8] = zf;
     }
     return ORC_OK;
 }

@@ -19,7 +19,8 @@ products; biases, pre-activations, GELU and its derivative, bias gradients
 and all sums stay in wide precision.  This models the kernels' arithmetic for
 a tight comparison; bf16=False is the exact FP64 definition.  Loss per sample:
     (1/4) sum_c (y_c - t_c)^2 + LAMBDA * BCE(sigmoid(y_4), label),
-    label = 1 when max_c |y_c - t_c| < CONF_TOL (no gradient through the label),
+    label = 1 when max_c |y_c - t_c| < conf_tol (default CONF_TOL; no gradient
+    through the label),
 averaged over the samples.
 """
 from __future__ import annotations
@@ -87,13 +88,14 @@ def forward(p, X, bf16=False):
     return y, dict(xs=xs, z1=z1, h1=h1, z2=z2, h2=h2, bf16=b)
 
 
-def loss_and_dy(y, T):
-    """Mean loss and dL/dy for targets T [n,4]."""
+def loss_and_dy(y, T, conf_tol=CONF_TOL):
+    """Mean loss and dL/dy for targets T [n,4]; the confidence label is
+    1[max_c |y_c - t_c| < conf_tol]."""
     y = np.asarray(y, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
     n = y.shape[0]
     err = y[:, :4] - T
-    label = (np.abs(err).max(axis=1) < CONF_TOL).astype(np.float64)
+    label = (np.abs(err).max(axis=1) < conf_tol).astype(np.float64)
     s = 1.0 / (1.0 + np.exp(-y[:, 4]))
     bce = -(label * np.log(np.maximum(s, 1e-300)) + (1 - label) * np.log(np.maximum(1 - s, 1e-300)))
     L = float(np.mean(0.25 * (err ** 2).sum(axis=1) + LAMBDA * bce))

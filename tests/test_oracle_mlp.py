@@ -200,9 +200,13 @@ def test_tail_column_closed_forms(oracle_lib, n, K, a):
         assert comp == pytest.approx(full[s], abs=1e-12)
         assert feat[s, 0] == pytest.approx(math.log1p(nt), abs=1e-12)
         assert feat[s, 1] == pytest.approx(nt * a, abs=1e-12)
-        for k in range(1, 5):
+        for k in (1, 2):
             assert feat[s, 1 + k] == pytest.approx(np.mean(zi ** k), abs=5e-5)
-        assert feat[s, 6:9] == pytest.approx(c, abs=1e-12)
+        # proxy composite of nt equal layers: alpha 1 - (1 - a)^nt, colour c * alpha
+        pa = 1 - (1 - a) ** nt
+        assert feat[s, 7] == pytest.approx(pa, abs=1e-12)
+        assert feat[s, 4:7] == pytest.approx(c * pa, abs=1e-12)
+        assert feat[s, 8] == pytest.approx(K / n, abs=5e-5)
 
 
 def test_tail_short_lists_have_no_row(oracle_lib):
@@ -233,3 +237,40 @@ def test_tail_focus_removes_proxy_opacity(oracle_lib):
     _, near, _, _ = fr.tail(synth.Hotspot((0.0, 0.0, -0.5), 100.0), st, K, w0, w1)
     assert far[0, 1] == pytest.approx((n + 1 - K) * 0.2, abs=1e-12)
     assert 0 < near[0, 1] < 1e-6
+
+
+def test_tail_proxy_composite_is_front_to_back(oracle_lib):
+    """Cells of increasing importance along the column give faces of
+    different proxy colour and opacity; the proxy composite must be the
+    front-to-back one (which differs from that of the reversed order)."""
+    orc = oracle_lib
+    n, K = 12, 2
+    m, cam = column_setup(n)
+    W = cam.width
+    pix = np.array([(W // 2) * W + W // 2])
+    sc = np.arange(n, dtype=np.float32) ** 2  # importance grows towards the back (cell k at z = -0.1 (n - k))
+    om = orc.Mesh(m.xyz, m.hex, cell_scalar=sc[::-1].copy())
+    ex = om.export()
+    fr = orc.Frame.from_camera(om, cam, pix)
+    w0, w1 = orc.view_depth_range(ex["pos_q"], cam.view_proj)
+    st = flat_style(tf_a_lo=0.1, tf_a_hi=0.7)
+    _, feat, _, _ = fr.tail(synth.Hotspot((50.0, 50.0, 50.0), 0.1), st, K, w0, w1)
+    zq = ex["pos_q"][:, 2] / 65536.0
+    lo, hi = np.array(st.tf_rgb_lo), np.array(st.tf_rgb_hi)
+    layers = []
+    for i in range(K, n + 1):  # cap face at z = -0.1 i
+        f = [f for f in range(om.F) if np.all(np.abs(zq[ex["face_v"][f]] + 0.1 * i) < 1e-4)]
+        assert len(f) == 1
+        tb = float(np.mean(ex["t_v"][ex["face_v"][f[0]]]))
+        layers.append((0.1 + 0.6 * tb, lo + (hi - lo) * tb))
+    C, A = np.zeros(3), 0.0
+    for al, col in layers:
+        C += (1 - A) * al * col
+        A += (1 - A) * al
+    Cr, Ar = np.zeros(3), 0.0  # the same layers in reversed depth order
+    for al, col in layers[::-1]:
+        Cr += (1 - Ar) * al * col
+        Ar += (1 - Ar) * al
+    assert abs(Ar - A) < 1e-12 and np.abs(Cr - C).max() > 1e-2  # the pin discriminates the order
+    assert feat[0, 7] == pytest.approx(A, abs=1e-12)
+    assert feat[0, 4:7] == pytest.approx(C, abs=1e-12)
