@@ -235,8 +235,12 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
  * the normalised view depth z_i = clamp((w_i - w0) / (w1 - w0), 0, 1)
  * (w_i = 2^20 / depth key, [w0, w1] = clip-w range of the mesh bbox corners
  * under the float camera matrix):
- *   f0 = log1p(n - K), f1 = sum a_i, f2..f5 = sum a_i z_i^k / sum a_i
- *   (k = 1..4), f6..f8 = sum a_i C_i / sum a_i (0 where sum a_i = 0).
+ *   f0 = log1p(n - K), f1 = sum a_i,
+ *   f2 = sum a_i z_i / sum a_i, f3 = sum a_i z_i^2 / sum a_i (0 where
+ *   sum a_i = 0),
+ *   f4..f7 = premultiplied RGBA of the proxies (a_i C_i, a_i) composited
+ *   front to back in depth order,
+ *   f8 = z_{K+1}, the depth where the tail starts.
  *
  * Network parameters: FP32 device vector of hexfc_mlp_param_count() = 5143
  * floats, in this order: mu[9], inv_sigma[9] (input standardisation,
@@ -249,10 +253,13 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
  * ---------------------------------------------------------------------- */
 
 /* Learned resolve of the lists of the last hexfc_build_fragment_lists (one
- * view).  Lists of at most t_sort fragments (length class 0) and lists of at
- * most K fragments are resolved exactly; for the others the exact head is
- * composed with the predicted tail (clamped to [0, 1]) when
- * sigmoid(y[4]) >= conf_min, else the pixel is resolved exactly (fallback).
+ * view).  Lists of at most t_sort fragments (length class 0) are resolved
+ * exactly; for longer lists the exact head is composed with the predicted
+ * tail (clamped to [0, 1]) when the list is longer than K and the pixel
+ * confidence 1 - (1 - A_head) * (1 - sigmoid(y[4])) is at least conf_min
+ * (the prediction is trusted, or the head hides the tail), else the pixel is
+ * resolved by the exact kernels (fallback; its result is then bit-identical
+ * to hexfc_resolve's).
  *   params      device float[5143] (see above)
  *   K           head length, 1..64
  *   conf_min    confidence threshold in [0, 1); 0 accepts every prediction
@@ -282,8 +289,9 @@ hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, co
  * device; status only, no error text).  n rows, row-major.
  * forward:  y[n][5] = MLP(x[n][9]).
  * loss:     per row, (1/4) sum_c (y_c - t_c)^2 + 0.1 * BCE(sigmoid(y_4), l),
- *           l = 1 if max_c |y_c - t_c| < 2e-3 else 0 (target t[n][4]);
- *           *loss_sum += sum over rows; dy[n][5] = d(mean loss)/dy.
+ *           l = 1 if max_c |y_c - t_c| < conf_tol else 0 (target t[n][4],
+ *           conf_tol > 0); *loss_sum += sum over rows;
+ *           dy[n][5] = d(mean loss)/dy.
  * backward: grad[5143] += d(sum dy * y)/d params (entries 0..17 untouched);
  *           the caller zeroes grad.
  * adam:     one Adam step (step counts from 1, bias-corrected) on entries
@@ -292,8 +300,8 @@ hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, co
  * EDEVICE (launch failure). */
 int64_t hexfc_mlp_param_count(void);
 hexfc_status hexfc_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream);
-hexfc_status hexfc_mlp_loss(const float *y, const float *target, int64_t n, float *dy, float *loss_sum,
-                            void *stream);
+hexfc_status hexfc_mlp_loss(const float *y, const float *target, int64_t n, float conf_tol, float *dy,
+                            float *loss_sum, void *stream);
 hexfc_status hexfc_mlp_backward(const float *params, const float *x, const float *dy, int64_t n, float *grad,
                                 void *stream);
 hexfc_status hexfc_mlp_adam_step(float *params, float *m, float *v, const float *grad, float lr, float beta1,

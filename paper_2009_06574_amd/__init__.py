@@ -88,7 +88,7 @@ def load():
                                    st),
         "hexfc_mlp_param_count": ([], i64),
         "hexfc_mlp_forward": ([P, P, i64, P, P], st),
-        "hexfc_mlp_loss": ([P, P, i64, P, P, P], st),
+        "hexfc_mlp_loss": ([P, P, i64, ct.c_float, P, P, P], st),
         "hexfc_mlp_backward": ([P, P, P, i64, P, P], st),
         "hexfc_mlp_adam_step": ([P, P, P, P, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_int, P], st),
         "hexfc_status_string": ([st], ct.c_char_p),
@@ -322,9 +322,10 @@ class Renderer:
 
     def kernel_times(self) -> dict:
         """Accumulated (ms, launches) per kernel since the last call (waits for the events)."""
-        ms = (ct.c_double * 16)()
-        n = (ct.c_uint64 * 16)()
-        self._check(self.lib.hexfc_get_kernel_times(self.ctx, ms, n, 16))
+        k = len(self.KERNELS)
+        ms = (ct.c_double * k)()
+        n = (ct.c_uint64 * k)()
+        self._check(self.lib.hexfc_get_kernel_times(self.ctx, ms, n, k))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS) if n[i]}
 
 
@@ -369,8 +370,9 @@ def mlp_forward(params, x, y=None):
     return y
 
 
-def mlp_loss(y, target, dy=None, loss_sum=None):
-    """(dy [n,5], loss_sum [1]): loss_sum accumulates the per-row losses."""
+def mlp_loss(y, target, dy=None, loss_sum=None, conf_tol=2e-3):
+    """(dy [n,5], loss_sum [1]): loss_sum accumulates the per-row losses; the
+    confidence label is max_c |y_c - t_c| < conf_tol."""
     import torch
     lib = load()
     y, target = _f32(y), _f32(target)
@@ -379,7 +381,8 @@ def mlp_loss(y, target, dy=None, loss_sum=None):
         dy = torch.empty((n, 5), dtype=torch.float32, device=y.device)
     if loss_sum is None:
         loss_sum = torch.zeros(1, dtype=torch.float32, device=y.device)
-    _status(lib.hexfc_mlp_loss(_ptr(y), _ptr(target), n, _ptr(dy), _ptr(loss_sum), _cur_stream(y)))
+    _status(lib.hexfc_mlp_loss(_ptr(y), _ptr(target), n, float(conf_tol), _ptr(dy), _ptr(loss_sum),
+                               _cur_stream(y)))
     return dy, loss_sum
 
 

@@ -105,6 +105,8 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
     const int64_t nt = (int64_t)tl.ntiles * nv;
     const int64_t np = nt * TP;
     const int64_t T = 2 * ctx->F;
+    if (np >= (int64_t(1) << 31))  // pixel ids are 32-bit (PIX_SKIP reserved)
+        FAIL(ctx, HEXFC_ERANGE, "%lld padded pixels in the batch exceed 2^31", (long long)np);
     TRY(grow(ctx, ctx->vscr, sizeof(int4) * ctx->V * nv));
     if (nv > 1) {
         const void *old = ctx->vert_b.p;
@@ -560,7 +562,7 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
     TRY(grow(ctx, ctx->l_head, sizeof(float4) * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_feat, sizeof(float) * NFEAT * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_pix, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
-    TRY(grow(ctx, ctx->l_fb, sizeof(uint32_t) * NCLASS * std::max<int64_t>(ctx->cls_cap, 1)));
+    TRY(grow(ctx, ctx->l_fb, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
     shade_params(ctx->h_views[0].sp, hot, style);
     TRY(upload_views(ctx, 1, s));
     ResolveArgs a = resolve_args(ctx, rgba_out);
@@ -578,13 +580,15 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
         enqueue_tail_features(ctx, a, K, head, feat, nullptr, pix, false, s);
         {
             ScopedTimer tm(ctx, s, KID_MLP);
-            launch_mlp_apply(params, feat, head, pix, rows, a, ctx->t_sort, K, conf_min, fb, ctx->cls_cap, stats,
-                             mask_out, s);
+            launch_mlp_apply(params, feat, head, pix, rows, a, ctx->t_sort, K, conf_min, fb, stats, mask_out, s);
         }
+        // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
         ScopedTimer tm(ctx, s, KID_FALLBACK);
+        int64_t base = 0;
         for (int c = 1; c < NCLASS - 1; ++c) {
-            if (!ctx->last_stats[ST_CLASS + c]) continue;
-            launch_resolve_class(c, fb + (int64_t)c * ctx->cls_cap, 0, stats + ST_FB + c, ctx->t_sort, a, s);
+            const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
+            if (nc) launch_resolve_class(c, fb + base, nc, nullptr, ctx->t_sort, a, s);
+            base += nc;
         }
     }
     HIPCHK(ctx, hipGetLastError());

@@ -177,6 +177,8 @@ struct ResolveArgs {
 };
 // npix > 0: exact grid for that many pixels.  npix_dev != nullptr: a fixed,
 // persistent grid that reads the class size from device memory (graph replay).
+// Long-list classes (1..6) skip list entries equal to PIX_SKIP.
+constexpr uint32_t PIX_SKIP = 0xffffffffu;
 void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
                           const ResolveArgs &a, hipStream_t s);
 
@@ -196,18 +198,20 @@ void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int 
 // W3[64][5], b3[5]; outputs y[5] = tail RGBA + confidence logit.
 constexpr int MLP_PARAMS = 18 + 9 * 64 + 64 + 64 * 64 + 64 + 64 * 5 + 5;
 void launch_mlp_forward(const float *params, const float *X, int64_t n, float *Y, hipStream_t s);
-void launch_mlp_loss(const float *Y, const float *T, int64_t n, float *dY, float *loss_sum, hipStream_t s);
+void launch_mlp_loss(const float *Y, const float *T, int64_t n, float conf_tol, float *dY, float *loss_sum,
+                     hipStream_t s);
 void launch_mlp_backward(const float *params, const float *X, const float *dY, int64_t n, float *grad,
                          hipStream_t s);
 void launch_adam(float *w, float *m, float *v, const float *g, int count, float lr, float b1, float b2, float eps,
                  int step, hipStream_t s);
-// Apply the network to n learned pixels and compose with their heads; pixels
-// with more than K fragments whose confidence is below conf_min are appended
-// to the per-class fallback lists (fb + c*fb_cap, sizes in stats[ST_FB + c]);
-// mask (nullable) gets 0 where the learned tail was used.
+// Apply the network to n learned pixels and compose with their heads.  fb[j]
+// receives pix[j] where row j needs the exact resolve (at most K fragments,
+// or confidence below conf_min), else PIX_SKIP; stats[ST_FB + c] counts the
+// fallback pixels of length class c; mask (nullable) gets 0 where the learned
+// tail was used.
 void launch_mlp_apply(const float *params, const float *feat, const float *head, const uint32_t *pix, int64_t n,
-                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, int64_t fb_cap,
-                      uint64_t *stats, uint8_t *mask, hipStream_t s);
+                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, uint64_t *stats,
+                      uint8_t *mask, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 }  // namespace hexfc

@@ -24,7 +24,7 @@ constexpr int NF = 9, NH = 64, NO = 5;
 constexpr int P_MU = 0, P_IS = 9, P_W1 = 18, P_B1 = P_W1 + NF * NH, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH,
               P_W3 = P_B2 + NH, P_B3 = P_W3 + NH * NO, P_END = P_B3 + NO;
 static_assert(P_END == MLP_PARAMS, "parameter layout");
-constexpr float LAMBDA = 0.1f, CONF_TOL = 2e-3f;
+constexpr float LAMBDA = 0.1f;
 
 __device__ __forceinline__ unsigned short f2bf(float x) {  // round to nearest even
     uint32_t u = __float_as_uint(x);
@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ p
 
 // ------------------------------------------------------------------ loss
 __global__ void __launch_bounds__(256) k_mlp_loss(const float *__restrict__ Y, const float *__restrict__ T, int64_t n,
-                                                  float *__restrict__ dY, float *__restrict__ loss_sum) {
+                                                  float conf_tol, float *__restrict__ dY,
+                                                  float *__restrict__ loss_sum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
     if (i < n) {
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(256) k_mlp_loss(const float *__restrict__ Y, c
             se += e[c] * e[c];
             dY[i * NO + c] = 0.5f * e[c] * inv_n;
         }
-        const float label = emax < CONF_TOL ? 1.f : 0.f;
+        const float label = emax < conf_tol ? 1.f : 0.f;
         const float yc = Y[i * NO + 4];
         const float s = 1.f / (1.f + expf(-yc));
         // BCE with logits, stable form: max(y,0) - y*label + log(1 + exp(-|y|))
@@ -348,21 +349,22 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 
 // ------------------------------------------------------------------ inference in the learned resolve
 // Row j: pixel pix[j] (global tile-major id) with head composite head[j] and
-// features feat[j].  Lists of at most K fragments are complete in the head
-// (exact).  Otherwise the network's tail is composed under the head when its
-// confidence logit clears logit_min; else the pixel goes to the fallback list
-// of its length class, to be resolved exactly.  mask (nullable, preset to 1
-// = exact) gets 0 where the learned tail was used.
+// features feat[j].  The network's tail is composed under the head when the
+// list is longer than K and the pixel confidence
+// 1 - (1 - A_head) (1 - sigmoid(y_4)) reaches conf_min; else fb[j] names the
+// pixel for the exact resolve.  mask (nullable, preset to 1 = exact) gets 0
+// where the learned tail was used.
 __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ params, const float *__restrict__ feat,
                                                    const float *__restrict__ head, const uint32_t *__restrict__ pix,
-                                                   int64_t n, ResolveArgs a, int t_sort, int K, float logit_min,
-                                                   uint32_t *__restrict__ fb, int64_t fb_cap,
-                                                   uint64_t *__restrict__ stats, uint8_t *__restrict__ mask) {
+                                                   int64_t n, ResolveArgs a, int t_sort, int K, float conf_min,
+                                                   uint32_t *__restrict__ fb, uint64_t *__restrict__ stats,
+                                                   uint8_t *__restrict__ mask) {
     __shared__ MlpLds L;
     mlp_load<false>(L, params);
     __syncthreads();
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    uint32_t nfb[NCLASS - 2] = {0, 0, 0, 0, 0, 0};  // fallback pixels per long-list class (wave total)
     for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t * 16 < n; t += waves) {
         const int64_t row = t * 16 + r;
         const bool valid = row < n;
@@ -371,24 +373,31 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         Fwd f;
         mlp_fwd16(L, xb, f);
         const float logit = __shfl(f.y[0], 16 + r);  // output 4 of row r lives in lane 16 + r
-        if (q != 0 || !valid) continue;
-        const uint32_t p = pix[row];
-        const uint32_t cnt = a.count[p];
+        // lanes 0..15 own the 16 rows of the tile
+        const bool active = q == 0 && valid;
+        uint32_t p = 0, cnt = 0;
+        float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (active) {
+            p = pix[row];
+            cnt = a.count[p];
+            h = reinterpret_cast<const float4 *>(head)[row];
+        }
+        // pixel confidence: the tail is either predicted well (network
+        // confidence) or hidden behind the head
+        const float conf = 1.f - (1.f - h.w) * (1.f - 1.f / (1.f + __expf(-logit)));
+        // exact resolve for lists of at most K fragments and low (or NaN) confidence
+        const bool fallback = active && (cnt <= (uint32_t)K || !(conf >= conf_min));
+        const int c = fallback ? length_class(cnt, t_sort) : -1;
+#pragma unroll
+        for (int cc = 1; cc < NCLASS - 1; ++cc) nfb[cc - 1] += (uint32_t)__popcll(__ballot(c == cc));
+        if (!active) continue;
+        fb[row] = fallback ? p : PIX_SKIP;
+        if (fallback) continue;
         const PixelRef pr = pixel_ref(a.tl, p);
         const int64_t o = (pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x;
-        float4 tail = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (cnt > (uint32_t)K) {
-            if (!(logit >= logit_min)) {  // low confidence (or NaN): exact fallback
-                const int c = length_class(cnt, t_sort);
-                const uint64_t slot = atomicAdd((unsigned long long *)&stats[ST_FB + c], 1ull);
-                if ((int64_t)slot < fb_cap) fb[(int64_t)c * fb_cap + slot] = p;
-                continue;
-            }
-            tail = make_float4(fminf(fmaxf(f.y[0], 0.f), 1.f), fminf(fmaxf(f.y[1], 0.f), 1.f),
-                               fminf(fmaxf(f.y[2], 0.f), 1.f), fminf(fmaxf(f.y[3], 0.f), 1.f));
-            if (mask) mask[o] = 0;
-        }
-        const float4 h = reinterpret_cast<const float4 *>(head)[row];
+        const float4 tail = make_float4(fminf(fmaxf(f.y[0], 0.f), 1.f), fminf(fmaxf(f.y[1], 0.f), 1.f),
+                                        fminf(fmaxf(f.y[2], 0.f), 1.f), fminf(fmaxf(f.y[3], 0.f), 1.f));
+        if (mask) mask[o] = 0;
         const float T = 1.f - h.w;
         const float C0 = h.x + T * tail.x, C1 = h.y + T * tail.y, C2 = h.z + T * tail.z, A = h.w + T * tail.w;
         const float Tb = 1.f - A;
@@ -396,6 +405,10 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         reinterpret_cast<float4 *>(a.rgba)[o] =
             make_float4(C0 + Tb * sp.bg[0], C1 + Tb * sp.bg[1], C2 + Tb * sp.bg[2], A);
     }
+    if (lane == 0)
+#pragma unroll
+        for (int cc = 1; cc < NCLASS - 1; ++cc)
+            if (nfb[cc - 1]) atomicAdd((unsigned long long *)&stats[ST_FB + cc], (unsigned long long)nfb[cc - 1]);
 }
 
 __global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
@@ -413,9 +426,10 @@ void launch_mlp_forward(const float *params, const float *X, int64_t n, float *Y
     if (n <= 0) return;
     k_mlp_forward<<<grid_for((n + 15) / 16, 4), 256, 0, s>>>(params, X, n, Y);
 }
-void launch_mlp_loss(const float *Y, const float *T, int64_t n, float *dY, float *loss_sum, hipStream_t s) {
+void launch_mlp_loss(const float *Y, const float *T, int64_t n, float conf_tol, float *dY, float *loss_sum,
+                     hipStream_t s) {
     if (n <= 0) return;
-    k_mlp_loss<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Y, T, n, dY, loss_sum);
+    k_mlp_loss<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Y, T, n, conf_tol, dY, loss_sum);
 }
 void launch_mlp_backward(const float *params, const float *X, const float *dY, int64_t n, float *grad,
                          hipStream_t s) {
@@ -428,12 +442,11 @@ void launch_adam(float *w, float *m, float *v, const float *g, int count, float 
     k_adam<<<(count + 255) / 256, 256, 0, s>>>(w, m, v, g, count, lr, b1, b2, eps, c1, c2);
 }
 void launch_mlp_apply(const float *params, const float *feat, const float *head, const uint32_t *pix, int64_t n,
-                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, int64_t fb_cap,
-                      uint64_t *stats, uint8_t *mask, hipStream_t s) {
+                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, uint64_t *stats,
+                      uint8_t *mask, hipStream_t s) {
     if (n <= 0) return;
-    const float logit_min = conf_min > 0.f ? logf(conf_min / (1.f - conf_min)) : -INFINITY;
-    k_mlp_apply<<<grid_for((n + 15) / 16, 4), 256, 0, s>>>(params, feat, head, pix, n, a, t_sort, K, logit_min, fb,
-                                                            fb_cap, stats, mask);
+    k_mlp_apply<<<grid_for((n + 15) / 16, 4), 256, 0, s>>>(params, feat, head, pix, n, a, t_sort, K, conf_min, fb,
+                                                            stats, mask);
 }
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
     if (n <= 0) return;
@@ -459,10 +472,11 @@ hexfc_status hexfc_mlp_forward(const float *params, const float *x, int64_t n, f
     return launched();
 }
 
-hexfc_status hexfc_mlp_loss(const float *y, const float *target, int64_t n, float *dy, float *loss_sum,
-                            void *stream) {
+hexfc_status hexfc_mlp_loss(const float *y, const float *target, int64_t n, float conf_tol, float *dy,
+                            float *loss_sum, void *stream) {
     if (n < 0 || (n > 0 && (!y || !target || !dy || !loss_sum))) return HEXFC_EINVAL;
-    hexfc::launch_mlp_loss(y, target, n, dy, loss_sum, (hipStream_t)stream);
+    if (!(conf_tol > 0.f)) return HEXFC_ERANGE;
+    hexfc::launch_mlp_loss(y, target, n, conf_tol, dy, loss_sum, (hipStream_t)stream);
     return launched();
 }
 

@@ -215,6 +215,7 @@ __global__ void __launch_bounds__(256) k_resolve_long(const uint32_t *__restrict
         const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
         if (wave >= total) continue;
         const uint32_t p = list[wave];
+        if (p == PIX_SKIP) continue;
         uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
         const uint64_t first = a.off[p] - a.off[a.pass_p0];
         if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
@@ -299,10 +300,14 @@ void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, cons
 }
 
 // ------------------------------------------------------------------ learned tail: head and tail features
-// Wave per pixel, as the long-list resolve: sort, then the first K positions
-// are shaded exactly and composited (head); the tail positions get the proxy
-// shading (face centre distance to the hotspot, mean corner importance) whose
-// sums make the 9 features; with TRAIN the tail is also shaded exactly and
+// Wave per pixel, as the long-list resolve: sort; the first K fragments are
+// moved to lanes 0..K-1, shaded exactly (one per lane) and composited in
+// order (head).  Every tail fragment gets the proxy shading of its face
+// (opacity from the mean corner importance and the focus factor at the face
+// centre, colour from the mean corner importance) from which the features
+// are accumulated: tail length, proxy opacity sum, opacity-weighted mean depth
+// and mean squared depth, the ordered composite of the proxies and the depth
+// where the tail starts.  With TRAIN the tail is also shaded exactly and
 // composited (the regression target).
 __device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, float &A, int lane) {
 #pragma unroll
@@ -349,60 +354,62 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     const ViewParams &vp = a.views[pr.view];
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    // head: sorted element l to lane l, one exact shade per lane
+    uint64_t hv = ~0ull;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const uint64_t t = __shfl(v[rr], lane / R);
+        if (lane % R == rr) hv = t;
+    }
+    float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
+    if (lane < K && (uint32_t)lane < n) {
+        const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(hv & 0xffffffffu), pr.x, pr.y);
+        H0 = fr.r;
+        H1 = fr.g;
+        H2 = fr.b;
+        HA = fr.a;
+    }
     const float zs = 1.f / (vp.w1 - vp.w0);
-    float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;  // head composite
-    float T0 = 0.f, T1 = 0.f, T2 = 0.f, TA = 0.f;  // exact tail composite
-    float sa = 0.f, sz1 = 0.f, sz2 = 0.f, sz3 = 0.f, sz4 = 0.f, sc0 = 0.f, sc1 = 0.f, sc2 = 0.f;
+    float T0 = 0.f, T1 = 0.f, T2 = 0.f, TA = 0.f;  // exact tail composite (TRAIN)
+    float P0 = 0.f, P1 = 0.f, P2 = 0.f, PA = 0.f;  // ordered proxy composite
+    float sa = 0.f, sz1 = 0.f, sz2 = 0.f, zf = 0.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t e = lane * R + r;
-        if (e >= n) continue;
+        if (e >= n || (int)e < K) continue;
         const uint32_t tri = (uint32_t)(v[r] & 0xffffffffu);
-        if ((int)e < K || TRAIN) {
+        if (TRAIN) {
             const Frag fr = shade(a.mesh, vert, sp, tri, pr.x, pr.y);
-            if ((int)e < K) {
-                const float T = 1.f - HA;
-                H0 += T * fr.r;
-                H1 += T * fr.g;
-                H2 += T * fr.b;
-                HA += T * fr.a;
-            } else {
-                const float T = 1.f - TA;
-                T0 += T * fr.r;
-                T1 += T * fr.g;
-                T2 += T * fr.b;
-                TA += T * fr.a;
-            }
+            const float T = 1.f - TA;
+            T0 += T * fr.r;
+            T1 += T * fr.g;
+            T2 += T * fr.b;
+            TA += T * fr.a;
         }
-        if ((int)e >= K) {
-            const float4 fp = a.mesh.face_px[tri >> 1];
-            const float dx = fp.x - sp.hc[0], dy = fp.y - sp.hc[1], dz = fp.z - sp.hc[2];
-            const float dist = fminf(sqrtf(dx * dx + dy * dy + dz * dz) * sp.inv_r, 1.f);
-            const float d2 = dist * dist;
-            const float al = (sp.a_lo + (sp.a_hi - sp.a_lo) * fp.w) * d2 * d2;
-            const float key = (float)(KMAX - (uint32_t)(v[r] >> 32));
-            const float z = fminf(fmaxf((1048576.f / key - vp.w0) * zs, 0.f), 1.f);
-            const float z2 = z * z;
-            sa += al;
-            sz1 += al * z;
-            sz2 += al * z2;
-            sz3 += al * z2 * z;
-            sz4 += al * z2 * z2;
-            sc0 += al * (sp.lo[0] + (sp.hi[0] - sp.lo[0]) * fp.w);
-            sc1 += al * (sp.lo[1] + (sp.hi[1] - sp.lo[1]) * fp.w);
-            sc2 += al * (sp.lo[2] + (sp.hi[2] - sp.lo[2]) * fp.w);
-        }
+        const float4 fp = a.mesh.face_px[tri >> 1];
+        const float dx = fp.x - sp.hc[0], dy = fp.y - sp.hc[1], dz = fp.z - sp.hc[2];
+        const float dist = fminf(sqrtf(dx * dx + dy * dy + dz * dz) * sp.inv_r, 1.f);
+        const float d2 = dist * dist;
+        const float al = (sp.a_lo + (sp.a_hi - sp.a_lo) * fp.w) * d2 * d2;
+        const float key = (float)(KMAX - (uint32_t)(v[r] >> 32));
+        const float z = fminf(fmaxf((1048576.f * __builtin_amdgcn_rcpf(key) - vp.w0) * zs, 0.f), 1.f);
+        sa += al;
+        sz1 += al * z;
+        sz2 += al * z * z;
+        const float T = 1.f - PA;
+        P0 += T * al * (sp.lo[0] + (sp.hi[0] - sp.lo[0]) * fp.w);
+        P1 += T * al * (sp.lo[1] + (sp.hi[1] - sp.lo[1]) * fp.w);
+        P2 += T * al * (sp.lo[2] + (sp.hi[2] - sp.lo[2]) * fp.w);
+        PA += T * al;
+        if ((int)e == K) zf = z;
     }
     over_reduce(H0, H1, H2, HA, lane);
     if (TRAIN) over_reduce(T0, T1, T2, TA, lane);
+    over_reduce(P0, P1, P2, PA, lane);
     sa = wave_sum(sa);
     sz1 = wave_sum(sz1);
     sz2 = wave_sum(sz2);
-    sz3 = wave_sum(sz3);
-    sz4 = wave_sum(sz4);
-    sc0 = wave_sum(sc0);
-    sc1 = wave_sum(sc1);
-    sc2 = wave_sum(sc2);
+    zf = wave_sum(zf);
     if (lane == 0) {
         const int64_t o = out_base + wave;
         const float inv = sa > 0.f ? 1.f / sa : 0.f;
@@ -411,11 +418,11 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         F[1] = sa;
         F[2] = sz1 * inv;
         F[3] = sz2 * inv;
-        F[4] = sz3 * inv;
-        F[5] = sz4 * inv;
-        F[6] = sc0 * inv;
-        F[7] = sc1 * inv;
-        F[8] = sc2 * inv;
+        F[4] = P0;
+        F[5] = P1;
+        F[6] = P2;
+        F[7] = PA;
+        F[8] = zf;
         reinterpret_cast<float4 *>(head)[o] = make_float4(H0, H1, H2, HA);
         if (TRAIN) reinterpret_cast<float4 *>(target)[o] = make_float4(T0, T1, T2, TA);
         pix_out[o] = rowmajor ? (uint32_t)((pr.view * a.tl.H + pr.y) * a.tl.W + pr.x) : p;
