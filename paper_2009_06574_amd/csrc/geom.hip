@@ -240,48 +240,78 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 }
 
 // ------------------------------------------------------------------ count / fill
-// One workgroup of TW*TH lanes per screen tile (lane = pixel).  The tile's bin
-// is consumed in batches of NT triangles: each lane sets up one triangle into
-// LDS, then every lane tests its pixel against the whole batch.  The count
-// pass also stores, per bin entry and wave, the 64-bit mask of covered
-// pixels; the fill pass reads those masks instead of testing coverage again
-// and skips the entries that cover nothing.
+// One workgroup of 512 lanes per screen tile: S = 512 / (TW*TH) groups of
+// TW*TH lanes (lane = pixel), each group taking one contiguous, equal chunk of
+// the tile's bin, so that the densest tiles are not walked by one wave alone.
+// A group consumes its chunk in batches of TW*TH triangles: each lane sets up
+// one triangle into LDS, then every lane tests its pixel against the batch.
+// The count pass also stores, per bin entry and wave, the 64-bit mask of
+// covered pixels; the fill pass reads those masks instead of testing coverage
+// again, first to count each group's fragments per pixel (which places the
+// group's records after those of the groups before it: the list order is the
+// bin order, as with a single group), then to write the records.
+constexpr int RASTER_WG = 512;
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
-                                                  const uint32_t *__restrict__ bins,
-                                                  const int4 *__restrict__ face_c,
-                                                  const int4 *__restrict__ vscr, int64_t V,
-                                                  uint32_t *__restrict__ count, uint64_t cap,
-                                                  uint64_t *__restrict__ masks) {
-    constexpr int NT = TW * TH, NW = NT / 64;
-    __shared__ CovSetup s_cov[NT];
+struct RasterShape {
+    static constexpr int NT = TW * TH, NW = NT / 64, S = RASTER_WG / NT;
+    static_assert(NT % 64 == 0 && RASTER_WG % NT == 0, "tile shape");
+};
+
+// chunk [c0, c1) of the tile's bin range [b0, b1) for group grp of S
+struct Chunk {
+    uint64_t c0, c1;
+    int iters;  // batches per group (the same for every group of the workgroup)
+};
+template <int NT, int S>
+__device__ __forceinline__ Chunk bin_chunk(uint64_t b0, uint64_t b1, int grp) {
+    const uint64_t per = (b1 - b0 + S - 1) / S;
+    Chunk c;
+    c.c0 = min(b0 + (uint64_t)grp * per, b1);
+    c.c1 = min(c.c0 + per, b1);
+    c.iters = (int)((per + NT - 1) / NT);
+    return c;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
+                                                     const uint32_t *__restrict__ bins,
+                                                     const int4 *__restrict__ face_c,
+                                                     const int4 *__restrict__ vscr, int64_t V,
+                                                     uint32_t *__restrict__ count, uint64_t cap,
+                                                     uint64_t *__restrict__ masks) {
+    using RS = RasterShape<TW, TH>;
+    constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
+    __shared__ CovSetup s_cov[S][NT];
+    __shared__ uint32_t s_n[S][NT];
+    const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
     const int64_t g = blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
     vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = t % TW, ly = t / TW;
+    const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
     const int dx = SUB * lx, dy = SUB * ly;
     const bool valid = (tx * TW + lx) < tl.W && (ty * TH + ly) < tl.H;
     // (bins beyond the capacity were not stored; the caller grows and redoes the frame)
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
+    const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
     uint32_t n = 0;
     KeySetup dummy;
-    for (uint64_t base = b0; base < b1; base += NT) {
-        const int m = (int)min((uint64_t)NT, b1 - base);
-        if ((int)threadIdx.x < m) {
+    for (int it = 0; it < ch.iters; ++it) {
+        const uint64_t base = ch.c0 + (uint64_t)it * NT;
+        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        if (t < m) {
             CovSetup cs;
-            tri_setup<false>(face_c, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
-                             dummy);
-            s_cov[threadIdx.x] = cs;
+            tri_setup<false>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, dummy);
+            s_cov[grp][t] = cs;
         }
         __syncthreads();
         uint64_t mine = 0;
         for (int j = 0; j < m; ++j) {
-            const bool c = valid && covers(s_cov[j], dx, dy);
+            const bool c = valid && covers(s_cov[grp][j], dx, dy);
             n += c ? 1u : 0u;
             const uint64_t bm = __ballot(c);
             if ((j & 63) == lane) mine = bm;
@@ -292,62 +322,87 @@ __global__ void __launch_bounds__(TW *TH) k_count(Tiling tl, const uint64_t *__r
         }
         __syncthreads();
     }
-    count[(size_t)g * NT + threadIdx.x] = n;
+    s_n[grp][t] = n;
+    __syncthreads();
+    if (grp == 0) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) tot += s_n[q][t];
+        count[(size_t)g * NT + t] = tot;
+    }
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
-                                                 const uint32_t *__restrict__ bins,
-                                                 const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
-                                                 int64_t V, const uint64_t *__restrict__ off,
-                                                 uint64_t *__restrict__ rec, uint64_t rec_cap, uint64_t cap,
-                                                 const uint64_t *__restrict__ masks) {
-    constexpr int NT = TW * TH, NW = NT / 64;
-    __shared__ KeySetup s_key[NT];
-    __shared__ uint64_t s_mask[NT * NW];
+__global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
+                                                    const uint32_t *__restrict__ bins,
+                                                    const int4 *__restrict__ face_c,
+                                                    const int4 *__restrict__ vscr, int64_t V,
+                                                    const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
+                                                    uint64_t rec_cap, uint64_t cap,
+                                                    const uint64_t *__restrict__ masks) {
+    using RS = RasterShape<TW, TH>;
+    constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
+    __shared__ KeySetup s_key[S][NT];
+    __shared__ uint64_t s_mask[S][NT * NW];
+    __shared__ uint32_t s_n[S][NT];
+    const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
     const int64_t g = g0 + blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
     vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = t % TW, ly = t / TW;
+    const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
     const int dx = SUB * lx, dy = SUB * ly;
     const uint64_t pass_base = off[(size_t)g0 * NT];
-    const uint64_t first = off[(size_t)g * NT + threadIdx.x] - pass_base;
+    const uint64_t first = off[(size_t)g * NT + t] - pass_base;
     uint64_t *dst = rec + first;
     // records beyond the workspace are dropped (the frame is then reported as overflowed)
     const uint64_t room = first < rec_cap ? rec_cap - first : 0;
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
+    const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
+    // sweep 1: this group's fragments per pixel, from the coverage masks
     uint32_t n = 0;
-    for (uint64_t base = b0; base < b1; base += NT) {
-        const int m = (int)min((uint64_t)NT, b1 - base);
-        if ((int)threadIdx.x < m) {
+    for (int it = 0; it < ch.iters; ++it) {
+        const uint64_t base = ch.c0 + (uint64_t)it * NT;
+        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        if (t < m) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) s_mask[grp][t * NW + w] = masks[(base + t) * NW + w];
+        }
+        __syncthreads();
+        for (int j = 0; j < m; ++j) n += (uint32_t)((s_mask[grp][j * NW + wave] >> lane) & 1ull);
+        __syncthreads();
+    }
+    s_n[grp][t] = n;
+    __syncthreads();
+    uint64_t k = 0;  // this group's first slot in the pixel's list
+    for (int q = 0; q < grp; ++q) k += s_n[q][t];
+    // sweep 2: depth keys and records
+    for (int it = 0; it < ch.iters; ++it) {
+        const uint64_t base = ch.c0 + (uint64_t)it * NT;
+        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        if (t < m) {
             uint64_t any = 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const uint64_t mk = masks[(base + threadIdx.x) * NW + w];
-                s_mask[threadIdx.x * NW + w] = mk;
-                any |= mk;
-            }
+            for (int w = 0; w < NW; ++w) any |= s_mask[grp][t * NW + w] = masks[(base + t) * NW + w];
             if (any) {
                 CovSetup cs;
                 KeySetup ks;
-                tri_setup<true>(face_c, vscr, bins[base + threadIdx.x], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs,
-                                ks);
-                s_key[threadIdx.x] = ks;
+                tri_setup<true>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
+                s_key[grp][t] = ks;
             }
         }
         __syncthreads();
         for (int j = 0; j < m; ++j) {
-            const uint64_t mk = s_mask[j * NW + wave];
+            const uint64_t mk = s_mask[grp][j * NW + wave];
             if (mk == 0) continue;
             if ((mk >> lane) & 1ull) {
-                const KeySetup &k = s_key[j];
-                const uint32_t key = depth_key(k, dx, dy);
-                if (n < room) dst[n] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)k.tri;
-                ++n;
+                const KeySetup &ks = s_key[grp][j];
+                const uint32_t key = depth_key(ks, dx, dy);
+                if (k < room) dst[k] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)ks.tri;
+                ++k;
             }
         }
         __syncthreads();
@@ -579,10 +634,10 @@ void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint
                   const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, hipStream_t s) {
     dim3 g((unsigned)((int64_t)tl.ntiles * nv));
 #define ARGS tl, tile_off, bins, face_c, vscr, V, count, cap, masks
-    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, 64, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, 128, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, 256, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, 256, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_count<32, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
 #undef ARGS
 }
 
@@ -592,10 +647,10 @@ void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_
     if (g1 <= g0) return;
     dim3 g((unsigned)(g1 - g0));
 #define ARGS tl, g0, tile_off, bins, face_c, vscr, V, off, rec, rec_cap, cap, masks
-    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, 64, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, 128, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, 256, 0, s>>>(ARGS)));
-    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, 256, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));
+    HEXFC_TILE_DISPATCH(32, 8, (k_fill<32, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
 #undef ARGS
 }
 
