@@ -332,6 +332,14 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
     }
 }
 
+// Fill: after the per-group counts, every batch of entries is expanded into
+// a compact list of (entry, pixel) fragments in LDS, and the group's lanes
+// take one fragment each (instead of one entry per wave step, which left most
+// lanes idle: an entry covers a few pixels of the tile).  Slots within a
+// pixel's list come from LDS counters, so records of one group may land in
+// any order within the group's range; every consumer sorts the list.
+constexpr int FILL_WINDOW = 1024;  // fragments expanded at a time per group
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
                                                     const uint32_t *__restrict__ bins,
@@ -342,24 +350,24 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
                                                     const uint64_t *__restrict__ masks) {
     using RS = RasterShape<TW, TH>;
     constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
+    static_assert(NT <= 256, "entry and pixel indices are packed in 8 bits each");
     __shared__ KeySetup s_key[S][NT];
     __shared__ uint64_t s_mask[S][NT * NW];
-    __shared__ uint32_t s_n[S][NT];
+    __shared__ uint32_t s_pos[S][NT];   // per pixel: next slot of the group
+    __shared__ uint32_t s_fb[S][NT];    // per entry: first fragment in the batch
+    __shared__ uint32_t s_wsum[S][NW];  // per wave: fragments (scan carry)
+    __shared__ uint16_t s_frag[S][FILL_WINDOW];
+    __shared__ uint64_t s_first[NT];
     const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
     const int64_t g = g0 + blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
     vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
-    const int lx = t % TW, ly = t / TW;
     const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
-    const int dx = SUB * lx, dy = SUB * ly;
     const uint64_t pass_base = off[(size_t)g0 * NT];
-    const uint64_t first = off[(size_t)g * NT + t] - pass_base;
-    uint64_t *dst = rec + first;
-    // records beyond the workspace are dropped (the frame is then reported as overflowed)
-    const uint64_t room = first < rec_cap ? rec_cap - first : 0;
+    if (grp == 0) s_first[t] = off[(size_t)g * NT + t] - pass_base;
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
     // sweep 1: this group's fragments per pixel, from the coverage masks
@@ -375,37 +383,87 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
         for (int j = 0; j < m; ++j) n += (uint32_t)((s_mask[grp][j * NW + wave] >> lane) & 1ull);
         __syncthreads();
     }
-    s_n[grp][t] = n;
+    s_pos[grp][t] = n;
     __syncthreads();
-    uint64_t k = 0;  // this group's first slot in the pixel's list
-    for (int q = 0; q < grp; ++q) k += s_n[q][t];
-    // sweep 2: depth keys and records
+    {  // the group's first slot per pixel: the fragments of the groups before it
+        uint32_t k = 0;
+        for (int q = 0; q < grp; ++q) k += s_pos[q][t];
+        __syncthreads();
+        s_pos[grp][t] = k;
+    }
+    // sweep 2: expand each batch into fragments, one lane per fragment
     for (int it = 0; it < ch.iters; ++it) {
         const uint64_t base = ch.c0 + (uint64_t)it * NT;
         const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        uint32_t c = 0;
         if (t < m) {
-            uint64_t any = 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) any |= s_mask[grp][t * NW + w] = masks[(base + t) * NW + w];
-            if (any) {
+            for (int w = 0; w < NW; ++w) {
+                const uint64_t mk = masks[(base + t) * NW + w];
+                s_mask[grp][t * NW + w] = mk;
+                c += (uint32_t)__popcll(mk);
+            }
+            if (c) {
                 CovSetup cs;
                 KeySetup ks;
                 tri_setup<true>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
                 s_key[grp][t] = ks;
             }
         }
-        __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            const uint64_t mk = s_mask[grp][j * NW + wave];
-            if (mk == 0) continue;
-            if ((mk >> lane) & 1ull) {
-                const KeySetup &ks = s_key[grp][j];
-                const uint32_t key = depth_key(ks, dx, dy);
-                if (k < room) dst[k] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)ks.tri;
-                ++k;
-            }
+        // exclusive scan of the entries' fragment counts over the group
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
         }
+        if (lane == 63) s_wsum[grp][wave] = incl;
         __syncthreads();
+        uint32_t carry = 0, total = 0, most = 0;  // most: the largest total of the workgroup's groups
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            uint32_t tq = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t ws = s_wsum[q][w];
+                if (q == grp) carry += w < wave ? ws : 0u;
+                tq += ws;
+            }
+            if (q == grp) total = tq;
+            most = max(most, tq);
+        }
+        const uint32_t fb = carry + incl - c;
+        // (every group runs the same number of windows: the loop holds barriers)
+        for (uint32_t w0 = 0; w0 < most; w0 += FILL_WINDOW) {
+            // entries write their fragments that fall into this window
+            if (c && fb < w0 + FILL_WINDOW && fb + c > w0) {
+                uint32_t pos = fb;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    uint64_t mk = s_mask[grp][t * NW + w];
+                    while (mk && pos < w0 + FILL_WINDOW) {
+                        const int b = __ffsll((long long)mk) - 1;
+                        mk &= mk - 1;
+                        if (pos >= w0) s_frag[grp][pos - w0] = (uint16_t)((t << 8) | (w * 64 + b));
+                        ++pos;
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t nf = w0 < total ? min((uint32_t)FILL_WINDOW, total - w0) : 0u;
+            for (uint32_t f = t; f < nf; f += NT) {
+                const uint32_t fr = s_frag[grp][f];
+                const int j = (int)(fr >> 8), pp = (int)(fr & 255u);
+                const KeySetup &ks = s_key[grp][j];
+                const uint32_t key = depth_key(ks, SUB * (pp % TW), SUB * (pp / TW));
+                const uint32_t slot = atomicAdd(&s_pos[grp][pp], 1u);
+                const uint64_t first = s_first[pp];
+                if (first < rec_cap && slot < rec_cap - first)
+                    rec[first + slot] = ((uint64_t)(KMAX - key) << 32) | (uint64_t)ks.tri;
+            }
+            __syncthreads();
+        }
+        __syncthreads();  // s_wsum, s_mask and s_key are rewritten by the next batch
     }
 }
 
