@@ -140,7 +140,10 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
 struct CovSetup {
     int a0, b0, c0, a1;
     int b1, c1, a2, b2;
-    int c2, pad0, pad1, pad2;
+    int c2;
+    int pad0;  // candidate pixel box in the tile: x0 | x1 << 8 | y0 << 16 | y1 << 24
+    int pad1;  // candidate pixels (0: the triangle misses the tile)
+    int pad2;
 };
 // Depth key of the same triangle: N(dx, dy) = n0 + na*dx + nb*dy (exact
 // int64), key = floor(N / D) with D = twice the oriented area.
@@ -203,14 +206,24 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ face_c, const
             ec[k] = (int)Eb;
         }
     }
+    // candidate pixels of the tile: centres inside the triangle's bounding box
+    const int mnx = min(v[0].x, min(v[1].x, v[2].x)), mxx = max(v[0].x, max(v[1].x, v[2].x));
+    const int mny = min(v[0].y, min(v[1].y, v[2].y)), mxy = max(v[0].y, max(v[1].y, v[2].y));
+    const int x0 = max(0, -((ox - mnx) >> 4)), x1 = min(ex / SUB, (mxx - ox) >> 4);  // ceil / floor of /16
+    const int y0 = max(0, -((oy - mny) >> 4)), y1 = min(ey / SUB, (mxy - oy) >> 4);
+    if (x0 > x1 || y0 > y1) reject = true;
     if (reject) {
         cs.a0 = cs.b0 = cs.a1 = cs.b1 = cs.a2 = cs.b2 = 0;
         cs.c0 = -1;
         cs.c1 = cs.c2 = 0;
+        cs.pad0 = 0;
+        cs.pad1 = 0;
     } else {
         cs.a0 = ea[0]; cs.b0 = eb[0]; cs.c0 = ec[0];
         cs.a1 = ea[1]; cs.b1 = eb[1]; cs.c1 = ec[1];
         cs.a2 = ea[2]; cs.b2 = eb[2]; cs.c2 = ec[2];
+        cs.pad0 = x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
+        cs.pad1 = (x1 - x0 + 1) * (y1 - y0 + 1);
     }
     if (WITH_KEY) {
         ks.n0 = n0;
@@ -273,6 +286,12 @@ __device__ __forceinline__ Chunk bin_chunk(uint64_t b0, uint64_t b1, int grp) {
     return c;
 }
 
+// Count: every batch of entries is expanded into its candidate (entry,
+// pixel) pairs -- the pixels of the tile inside the triangle's bounding box
+// -- one lane per pair; LDS atomics accumulate the per-pixel counts and the
+// entries' coverage masks.
+constexpr int RASTER_WINDOW = 1024;  // pairs / fragments expanded at a time per group
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
                                                      const uint32_t *__restrict__ bins,
@@ -282,52 +301,95 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
                                                      uint64_t *__restrict__ masks) {
     using RS = RasterShape<TW, TH>;
     constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
+    static_assert(NT <= 256, "entry and pixel indices are packed in 8 bits each");
     __shared__ CovSetup s_cov[S][NT];
-    __shared__ uint32_t s_n[S][NT];
+    __shared__ uint32_t s_cnt[S][NT];
+    __shared__ unsigned long long s_macc[S][NT * NW];
+    __shared__ uint32_t s_wsum[S][NW];
+    __shared__ uint16_t s_cand[S][RASTER_WINDOW];
     const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
     const int64_t g = blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
     vscr += view * V;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
-    const int lx = t % TW, ly = t / TW;
     const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
-    const int dx = SUB * lx, dy = SUB * ly;
-    const bool valid = (tx * TW + lx) < tl.W && (ty * TH + ly) < tl.H;
+    const int vw = tl.W - tx * TW, vh = tl.H - ty * TH;  // valid pixels: lx < vw, ly < vh
     // (bins beyond the capacity were not stored; the caller grows and redoes the frame)
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
-    uint32_t n = 0;
+    s_cnt[grp][t] = 0;
     KeySetup dummy;
     for (int it = 0; it < ch.iters; ++it) {
         const uint64_t base = ch.c0 + (uint64_t)it * NT;
         const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        uint32_t c = 0;
+        int box = 0;
         if (t < m) {
             CovSetup cs;
             tri_setup<false>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, dummy);
             s_cov[grp][t] = cs;
+            c = (uint32_t)cs.pad1;
+            box = cs.pad0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) s_macc[grp][t * NW + w] = 0ull;
         }
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_wsum[grp][wave] = incl;
         __syncthreads();
-        uint64_t mine = 0;
-        for (int j = 0; j < m; ++j) {
-            const bool c = valid && covers(s_cov[grp][j], dx, dy);
-            n += c ? 1u : 0u;
-            const uint64_t bm = __ballot(c);
-            if ((j & 63) == lane) mine = bm;
-            if ((j & 63) == 63 || j == m - 1) {
-                const int e = (j & ~63) + lane;
-                if (e < m) masks[(base + e) * NW + wave] = mine;
+        uint32_t carry = 0, total = 0, most = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            uint32_t tq = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t ws = s_wsum[q][w];
+                if (q == grp) carry += w < wave ? ws : 0u;
+                tq += ws;
             }
+            if (q == grp) total = tq;
+            most = max(most, tq);
         }
-        __syncthreads();
+        const uint32_t cb = carry + incl - c;
+        // (every group runs the same number of windows: the loop holds barriers)
+        for (uint32_t w0 = 0; w0 < most; w0 += RASTER_WINDOW) {
+            if (c && cb < w0 + RASTER_WINDOW && cb + c > w0) {
+                const int x0 = box & 255, x1 = (box >> 8) & 255, y0 = (box >> 16) & 255, y1 = (box >> 24) & 255;
+                uint32_t pos = cb;
+                for (int yy = y0; yy <= y1 && pos < w0 + RASTER_WINDOW; ++yy)
+                    for (int xx = x0; xx <= x1 && pos < w0 + RASTER_WINDOW; ++xx, ++pos)
+                        if (pos >= w0) s_cand[grp][pos - w0] = (uint16_t)((t << 8) | (yy * TW + xx));
+            }
+            __syncthreads();
+            const uint32_t nf = w0 < total ? min((uint32_t)RASTER_WINDOW, total - w0) : 0u;
+            for (uint32_t f = t; f < nf; f += NT) {
+                const uint32_t pr = s_cand[grp][f];
+                const int j = (int)(pr >> 8), pp = (int)(pr & 255u);
+                const int lx = pp % TW, ly = pp / TW;
+                if (lx < vw && ly < vh && covers(s_cov[grp][j], SUB * lx, SUB * ly)) {
+                    atomicAdd(&s_cnt[grp][pp], 1u);
+                    atomicOr(&s_macc[grp][j * NW + (pp >> 6)], 1ull << (pp & 63));
+                }
+            }
+            __syncthreads();
+        }
+        if (t < m) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) masks[(base + t) * NW + w] = s_macc[grp][t * NW + w];
+        }
+        __syncthreads();  // s_cov, s_macc and s_wsum are rewritten by the next batch
     }
-    s_n[grp][t] = n;
     __syncthreads();
     if (grp == 0) {
         uint32_t tot = 0;
 #pragma unroll
-        for (int q = 0; q < S; ++q) tot += s_n[q][t];
+        for (int q = 0; q < S; ++q) tot += s_cnt[q][t];
         count[(size_t)g * NT + t] = tot;
     }
 }
@@ -338,7 +400,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
 // lanes idle: an entry covers a few pixels of the tile).  Slots within a
 // pixel's list come from LDS counters, so records of one group may land in
 // any order within the group's range; every consumer sorts the list.
-constexpr int FILL_WINDOW = 1024;  // fragments expanded at a time per group
+constexpr int FILL_WINDOW = RASTER_WINDOW;
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
