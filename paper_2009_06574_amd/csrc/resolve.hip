@@ -237,33 +237,54 @@ __global__ void __launch_bounds__(256) k_resolve_long(const uint32_t *__restrict
             }
         }
         if (a.rgba) {
+            // Shade in rounds of 64 sorted fragments (element 64k + l to lane
+            // l), blend each round with the ordered "over" reduction, and stop
+            // once the pixel is opaque to within 2^-20: the fragments behind
+            // add less than that to any channel.
             const ShadeParams &sp = a.views[pr.view].sp;
             const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
-            float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;  // blended rounds (uniform over the wave)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t e = lane * R + r;
+            for (int k = 0; k < R; ++k) {
+                if (64u * k >= n) break;
+                const uint32_t e = 64u * k + lane;
+                uint64_t x = ~0ull;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const uint64_t t = __shfl(v[rr], (int)(e / R));
+                    if ((int)(e % R) == rr) x = t;
+                }
+                float c0 = 0.f, c1 = 0.f, c2 = 0.f, ca = 0.f;
                 if (e < n) {
-                    const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(v[r] & 0xffffffffu), pr.x, pr.y);
-                    const float T = 1.f - A;
-                    C0 += T * fr.r;
-                    C1 += T * fr.g;
-                    C2 += T * fr.b;
-                    A += T * fr.a;
+                    const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(x & 0xffffffffu), pr.x, pr.y);
+                    c0 = fr.r;
+                    c1 = fr.g;
+                    c2 = fr.b;
+                    ca = fr.a;
                 }
-            }
-            // ordered reduction: lane l's run precedes lane l+1's
+                // ordered reduction: lane l's fragment precedes lane l+1's
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o),
-                            qa = __shfl_down(A, o);
-                if ((lane & (2 * o - 1)) == 0) {
-                    const float T = 1.f - A;
-                    C0 += T * q0;
-                    C1 += T * q1;
-                    C2 += T * q2;
-                    A += T * qa;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const float q0 = __shfl_down(c0, o), q1 = __shfl_down(c1, o), q2 = __shfl_down(c2, o),
+                                qa = __shfl_down(ca, o);
+                    if ((lane & (2 * o - 1)) == 0) {
+                        const float T = 1.f - ca;
+                        c0 += T * q0;
+                        c1 += T * q1;
+                        c2 += T * q2;
+                        ca += T * qa;
+                    }
                 }
+                c0 = __shfl(c0, 0);
+                c1 = __shfl(c1, 0);
+                c2 = __shfl(c2, 0);
+                ca = __shfl(ca, 0);
+                const float T = 1.f - A;
+                C0 += T * c0;
+                C1 += T * c1;
+                C2 += T * c2;
+                A += T * ca;
+                if (1.f - A < T_EPS) break;
             }
             if (lane == 0) {
                 const float T = 1.f - A;
