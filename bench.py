@@ -27,23 +27,79 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(mesh, cam, hot, style, row_step: int):
-    """Time the FP64 oracle (as it stands) on every `row_step`-th row of one view."""
+def cpu_baseline(mesh, cams, hots, styles, row_step: int):
+    """Time the FP64 oracle (as it stands) on every `row_step`-th row of the given views."""
     import numpy as np
 
     import oracle
-    W, H = cam.width, cam.height
-    rows = np.arange(0, H, row_step)
-    pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int32)
     om = oracle.Mesh.from_synth(mesh)
-    t0 = time.perf_counter()
-    fr = oracle.Frame.from_camera(om, cam, pixels=pix)
-    fr.shade(hot, style)
-    dt = time.perf_counter() - t0
-    return dict(value=fr.nfrag / dt, unit="fragments/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"view 0, every {row_step}th row ({pix.size} of {W * H} pixels, {fr.nfrag} fragments), "
-                       f"{dt:.1f} s; mesh attribute preprocessing excluded",
+    frags, npx, dt = 0, 0, 0.0
+    for cam, hot, style in zip(cams, hots, styles):
+        W, H = cam.width, cam.height
+        rows = np.arange(0, H, row_step)
+        pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int32)
+        t0 = time.perf_counter()
+        fr = oracle.Frame.from_camera(om, cam, pixels=pix)
+        fr.shade(hot, style)
+        dt += time.perf_counter() - t0
+        frags += fr.nfrag
+        npx += pix.size
+    return dict(value=frags / dt, unit="fragments/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"views 0-{len(cams) - 1}, every {row_step}th row ({npx} pixels, {frags} fragments), "
+                       f"{dt:.1f} s of raster + sort + shade + blend; mesh attribute preprocessing excluded",
                 seconds=dt)
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, scaled by the copy calibration; None when there is no
+    summary for it or the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_counters_bent128_1080p.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(x.split("=", 1) for x in line.split()[1:])
+        if kv.get("kernel") != kernel:
+            continue
+        src = os.path.join(ROOT, kv["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["sha256"]:
+            return None
+        return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                         float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
+
+
+def learned_tail(r, mesh, conf_min, seeds=range(1001, 1005)):
+    """Exact vs learned-tail resolve on the same lists: held-out random views
+    of the benchmark mesh (the network was trained on seeds 1-1000)."""
+    import numpy as np
+    import torch
+
+    from paper_2009_06574_amd import tail
+    p_np, meta = tail.load_weights()
+    params = torch.tensor(p_np, device="cuda")
+    res = []
+    for cam, hot, st in tail._views(mesh, seeds, 1920, 1080):
+        d = tail.evaluate_view(r, cam, hot, st, params, meta["K"], (conf_min,), reps=5)
+        res.append(d)
+        lv = d["learned"][str(conf_min)]
+        log(f"[bench] learned tail: exact {d['ms_exact']:.3f} ms, learned {lv['ms']:.3f} ms, "
+            f"PSNR {lv['psnr']:.2f} dB, fallback {lv['fallback_pixels']} of {d['long_pixels']} long pixels")
+    L = [d["learned"][str(conf_min)] for d in res]
+    ms_e = float(np.mean([d["ms_exact"] for d in res]))
+    ms_l = float(np.mean([x["ms"] for x in L]))
+    return dict(K=meta["K"], conf_min=conf_min, views=f"held-out random views, seeds {seeds[0]}-{seeds[-1]}",
+                resolve_exact_ms=round(ms_e, 4), resolve_learned_ms=round(ms_l, 4), speedup=round(ms_e / ms_l, 3),
+                psnr_db_mean=round(float(np.mean([x["psnr"] for x in L])), 2),
+                psnr_db_min=round(float(min(x["psnr"] for x in L)), 2),
+                fallback_frac=round(float(np.sum([x["fallback_pixels"] for x in L]) /
+                                          max(1, np.sum([d["long_pixels"] for d in res]))), 4),
+                psnr_db_k_truncation=round(float(np.mean([d["psnr_truncated"] for d in res])), 2),
+                psnr_db_proxy_tail=round(float(np.mean([d["psnr_proxy"] for d in res])), 2))
 
 
 def main():
@@ -53,7 +109,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-row-step", type=int, default=1)
+    ap.add_argument("--cpu-views", type=int, default=3, help="views timed for the CPU oracle baseline")
     ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-tail resolve comparison")
+    ap.add_argument("--conf-min", type=float, default=0.5, help="learned tail: pixel confidence threshold")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (scale for HBM counters) and exit")
     args = ap.parse_args()
@@ -136,18 +195,25 @@ def main():
     dom = max(alg, key=lambda k: kt[k][0])
     ms_dom, n_dom = kt[dom]
     achieved = (alg[dom] / n_dom) / (ms_dom / n_dom * 1e-3) / 1e9
+    traffic = measured_traffic(dom) if args.grid == 128 else None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else int(traffic), kernel=dom,
                     avg_launch_ms=round(ms_dom / n_dom, 4),
                     bytes_per_launch=int(alg[dom] / n_dom))
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
     log(f"[bench] per-frame kernel ms: {kernel_ms}")
     log(f"[bench] dominant {dom}: {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_tail(r, mesh, args.conf_min)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        cpu = cpu_baseline(mesh, cams[0], hots[0], styles[0], args.cpu_row_step)
+        cpu = cpu_baseline(mesh, cams[:args.cpu_views], hots[:args.cpu_views], styles[:args.cpu_views],
+                           args.cpu_row_step)
         log(f"[bench] oracle {cpu['value'] / 1e6:.2f} M fragments/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
         cpu.pop("seconds")
 
@@ -169,6 +235,7 @@ def main():
                    "fragments_per_frame": frags / args.steps, "workspace_GB": 8},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_tail": learned,
         "detail": {"kernel_ms_per_frame": kernel_ms,
                    "paper_context": "cubic128 (2,097,152 cells) at 1920x1080 on an RTX 2070 SUPER: "
                                     "147.3 ms/frame (45.8 F+C + 101.5 PPFL), other mesh and hardware"},
