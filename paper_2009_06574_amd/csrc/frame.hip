@@ -142,7 +142,6 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     const int64_t TP = (int64_t)tl.TW * tl.TH;
     const int64_t nt = (int64_t)tl.ntiles * nv;
     const int64_t np = nt * TP;
-    const int64_t T = 2 * ctx->F;
     uint64_t *stats = ctx->stats.as<uint64_t>();
     const int4 *fc = ctx->face_c.as<int4>();
     int4 *vscr = ctx->vscr.as<int4>();
@@ -157,13 +156,13 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_COUNT);
-        launch_tri_bin_count(fc, T, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), s);
+        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), s);
         launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>(), nt, ctx->tile_off.as<uint64_t>(),
                             ctx->scan_tmp.as<uint64_t>(), stats + ST_BINS, s);
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_SCATTER);
-        launch_tri_bin_scatter(fc, T, nv, vscr, ctx->V, tl, ctx->tile_off.as<uint64_t>(),
+        launch_tri_bin_scatter(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_off.as<uint64_t>(),
                                ctx->tile_fill.as<uint32_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, s);
     }
     {

@@ -62,13 +62,8 @@ __device__ __forceinline__ void tri_ids(const int4 c, int t, int &a, int &b, int
 
 // Screen-tile range of a triangle's pixel-centre bounding box; false when the
 // triangle is culled (flagged vertex, zero snapped area, nothing on screen).
-__device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
-                                               int64_t tri, const Tiling &tl, int &tx0, int &tx1, int &ty0,
-                                               int &ty1) {
-    int4 c = face_c[tri >> 1];
-    int ia, ib, ic;
-    tri_ids(c, (int)(tri & 1), ia, ib, ic);
-    int4 a = vscr[ia], b = vscr[ib], d = vscr[ic];
+__device__ __forceinline__ bool tri_tile_range(const int4 a, const int4 b, const int4 d, const Tiling &tl, int &tx0,
+                                               int &tx1, int &ty0, int &ty1) {
     if (a.w | b.w | d.w) return false;
     long long area = (long long)(b.x - a.x) * (d.y - a.y) - (long long)(b.y - a.y) * (d.x - a.x);
     if (area == 0) return false;
@@ -91,40 +86,80 @@ __device__ __forceinline__ bool tri_tile_range(const int4 *__restrict__ face_c, 
     return true;
 }
 
-// Triangle binning.  Each triangle adds itself to every screen tile its
-// pixel-centre bounding box overlaps.  Consecutive faces are mesh
-// neighbours, so the 64 triangles of a wave hit few distinct tiles: the lanes
-// that hit the same tile are merged into one atomic (leader election by
-// ballot), and each gets its rank inside the merged group.
+// Triangle binning, one lane per face (its two triangles share the corner
+// loads).  Each triangle adds itself to every screen tile its pixel-centre
+// bounding box overlaps.  Consecutive faces are mesh neighbours, so the 64
+// faces of a wave hit few distinct tiles: the lanes that hit the same tile
+// are merged into one atomic (leader election by ballot), and each gets its
+// rank inside the merged group.  The grouping uses ballots only; the group
+// leaders then issue their atomics together, so their latencies overlap.
+// The order of a tile's entries is not fixed; nothing downstream depends on
+// it.
 template <bool SCATTER>
-__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t T, int64_t NVT,
+__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t F, int64_t NVF,
                                                  const int4 *__restrict__ vscr, int64_t V, Tiling tl,
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
                                                  uint32_t *__restrict__ bins, uint64_t cap) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t view = i < NVT ? i / T : 0, t = i - view * T;
-    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
-    const bool ok = i < NVT && tri_tile_range(face_c, vscr + view * V, t, tl, tx0, tx1, ty0, ty1);
+    const int64_t view = i < NVF ? i / F : 0, f = i - view * F;
+    int r0[4] = {0, -1, 0, -1}, r1[4] = {0, -1, 0, -1};  // tile ranges of triangles 0 and 1: x0, x1, y0, y1
+    bool ok0 = false, ok1 = false;
+    if (i < NVF) {
+        const int4 c = face_c[f];
+        const int4 *vs = vscr + view * V;
+        const int4 p0 = vs[c.x], p1 = vs[c.y], p2 = vs[c.z], p3 = vs[c.w];
+        ok0 = tri_tile_range(p0, p1, p2, tl, r0[0], r0[1], r0[2], r0[3]);
+        ok1 = tri_tile_range(p0, p2, p3, tl, r1[0], r1[1], r1[2], r1[3]);
+    }
     const int64_t tile0 = view * tl.ntiles;
-    const int nx = ok ? tx1 - tx0 + 1 : 1;
-    const int n = ok ? nx * (ty1 - ty0 + 1) : 0;
+    // union of the two ranges; a tile of it takes the face's triangles that overlap it
+    int u[4] = {0, -1, 0, -1};
+    if (ok0 || ok1) {
+        u[0] = min(ok0 ? r0[0] : r1[0], ok1 ? r1[0] : r0[0]);
+        u[1] = max(ok0 ? r0[1] : r1[1], ok1 ? r1[1] : r0[1]);
+        u[2] = min(ok0 ? r0[2] : r1[2], ok1 ? r1[2] : r0[2]);
+        u[3] = max(ok0 ? r0[3] : r1[3], ok1 ? r1[3] : r0[3]);
+    }
+    const int nx = u[1] - u[0] + 1;
+    const int n = (ok0 || ok1) ? nx * (u[3] - u[2] + 1) : 0;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (int k = 0; __any(k < n); ++k) {
-        const int64_t tile = (k < n) ? tile0 + (ty0 + k / nx) * tl.ntx + tx0 + k % nx : -1;
+        int64_t tile = -1;
+        bool h0 = false, h1 = false;
+        if (k < n) {
+            const int x = u[0] + k % nx, y = u[2] + k / nx;
+            h0 = ok0 && x >= r0[0] && x <= r0[1] && y >= r0[2] && y <= r0[3];
+            h1 = ok1 && x >= r1[0] && x <= r1[1] && y >= r1[2] && y <= r1[3];
+            if (h0 || h1) tile = tile0 + (int64_t)y * tl.ntx + x;
+        }
+        // group the lanes by tile (ballots only), then one atomic per group,
+        // all groups' atomics in flight together
         unsigned long long pend = __ballot(tile >= 0);
+        int my_leader = lane;
+        unsigned my_rank = 0, lead_count = 0;
         while (pend) {
             const int leader = __ffsll((long long)pend) - 1;
             const int64_t lead_tile = __shfl(tile, leader);
-            const unsigned long long same = __ballot(tile == lead_tile);
-            unsigned base = 0;
-            if (lane == leader) base = atomicAdd(&tile_ctr[lead_tile], (unsigned)__popcll(same));
-            base = __shfl(base, leader);
-            if (SCATTER && tile == lead_tile) {
-                const uint64_t idx = tile_off[lead_tile] + base + (uint64_t)__popcll(same & below);
-                if (idx < cap) bins[idx] = (uint32_t)t;
+            const bool mine = tile == lead_tile;
+            const unsigned long long m0 = __ballot(mine && h0), m1 = __ballot(mine && h1);
+            if (mine) {
+                my_leader = leader;
+                my_rank = (unsigned)(__popcll(m0 & below) + __popcll(m1 & below));
             }
-            pend &= ~same;
+            if (lane == leader) lead_count = (unsigned)(__popcll(m0) + __popcll(m1));
+            pend &= ~__ballot(mine);
+        }
+        unsigned base = 0;
+        if (tile >= 0 && my_leader == lane) base = atomicAdd(&tile_ctr[tile], lead_count);
+        base = __shfl(base, my_leader);
+        if (SCATTER && tile >= 0) {
+            uint64_t idx = tile_off[tile] + base + my_rank;
+            if (h0) {
+                if (idx < cap) bins[idx] = (uint32_t)(2 * f);
+                ++idx;
+            }
+            if (h1 && idx < cap) bins[idx] = (uint32_t)(2 * f + 1);
         }
     }
 }
@@ -731,19 +766,19 @@ void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *vie
     const int64_t n = V * nv;
     if (n > 0) k_transform<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(posq, V, n, views, W, H, vert, vscr);
 }
-void launch_tri_bin_count(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                           uint32_t *tile_cnt, hipStream_t s) {
-    const int64_t n = T * nv;
+    const int64_t n = F * nv;
     if (n > 0)
-        k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, T, n, vscr, V, tl, tile_cnt,
+        k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_cnt,
                                                                           nullptr, nullptr, 0);
 }
-void launch_tri_bin_scatter(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+void launch_tri_bin_scatter(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                             const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             hipStream_t s) {
-    const int64_t n = T * nv;
+    const int64_t n = F * nv;
     if (n > 0)
-        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, T, n, vscr, V, tl, tile_fill,
+        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_fill,
                                                                          tile_off, bins, bin_cap);
 }
 

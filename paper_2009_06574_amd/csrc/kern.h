@@ -136,9 +136,9 @@ __device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
 // ---------------------------------------------------------------- launchers (geom.hip)
 void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *views, int W, int H, VertRec *vert,
                       int4 *vscr, hipStream_t s);
-void launch_tri_bin_count(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                           uint32_t *tile_cnt, hipStream_t s);
-void launch_tri_bin_scatter(const int4 *face_c, int64_t T, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
+void launch_tri_bin_scatter(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
                             const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             hipStream_t s);
 // masks: per bin entry and wave, the 64-bit coverage mask (written by count, read by fill)
