@@ -122,6 +122,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
     TRY(grow(ctx, ctx->tile_fill, sizeof(uint32_t) * nt));
     TRY(grow(ctx, ctx->tile_off, sizeof(uint64_t) * (nt + 1)));
     TRY(grow(ctx, ctx->count, sizeof(uint32_t) * np));
+    TRY(grow(ctx, ctx->gpre, sizeof(uint32_t) * nt * RASTER_WG));
     TRY(grow(ctx, ctx->off, sizeof(uint64_t) * (np + 1)));
     TRY(grow(ctx, ctx->scan_tmp, sizeof(uint64_t) * std::max(scan_tmp_elems(np), scan_tmp_elems(nt))));
     if (ctx->cls_cap < np) {
@@ -168,7 +169,7 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     {
         ScopedTimer tm(ctx, s, KID_COUNT);
         launch_count(tl, nv, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, fc, vscr, ctx->V,
-                     ctx->count.as<uint32_t>(), ctx->masks.as<uint64_t>(), s);
+                     ctx->count.as<uint32_t>(), ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
     }
     {
         ScopedTimer tm(ctx, s, KID_SCAN);
@@ -270,7 +271,7 @@ void timed_fill(hexfc_ctx *ctx, int64_t g0, int64_t g1, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_FILL);
     launch_fill(ctx->tl, g0, g1, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
                 ctx->face_c.as<int4>(), ctx->vscr.as<int4>(), ctx->V, ctx->off.as<uint64_t>(), ctx->ws,
-                ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), s);
+                ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
 }
 
 }  // namespace
@@ -410,7 +411,7 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
         enqueue_front(ctx, n, ctx->tl, cs, false);
         launch_fill(ctx->tl, 0, (int64_t)ctx->tl.ntiles * n, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(),
                     ctx->bin_cap, ctx->face_c.as<int4>(), ctx->vscr.as<int4>(), ctx->V, ctx->off.as<uint64_t>(),
-                    ctx->ws, ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), cs);
+                    ctx->ws, ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), cs);
         ResolveArgs a = resolve_args(ctx, rgba_out);
         launch_classes(ctx, a, nullptr, ctx->stats.as<uint64_t>() + ST_CLASS, cs);
         e = hipStreamEndCapture(cs, &g.graph);

@@ -294,11 +294,9 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 // A group consumes its chunk in batches of TW*TH triangles: each lane sets up
 // one triangle into LDS, then every lane tests its pixel against the batch.
 // The count pass also stores, per bin entry and wave, the 64-bit mask of
-// covered pixels; the fill pass reads those masks instead of testing coverage
-// again, first to count each group's fragments per pixel (which places the
-// group's records after those of the groups before it: the list order is the
-// bin order, as with a single group), then to write the records.
-constexpr int RASTER_WG = 512;
+// covered pixels, and per group and pixel the fragments of the groups before
+// it; the fill pass reads the masks instead of testing coverage again and
+// places each group's records after those of the groups before it.
 
 template <int TW, int TH>
 struct RasterShape {
@@ -333,7 +331,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
                                                      const int4 *__restrict__ face_c,
                                                      const int4 *__restrict__ vscr, int64_t V,
                                                      uint32_t *__restrict__ count, uint64_t cap,
-                                                     uint64_t *__restrict__ masks) {
+                                                     uint64_t *__restrict__ masks, uint32_t *__restrict__ gpre) {
     using RS = RasterShape<TW, TH>;
     constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
     static_assert(NT <= 256, "entry and pixel indices are packed in 8 bits each");
@@ -421,16 +419,18 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
         __syncthreads();  // s_cov, s_macc and s_wsum are rewritten by the next batch
     }
     __syncthreads();
-    if (grp == 0) {
-        uint32_t tot = 0;
+    uint32_t before = 0, tot = 0;  // fragments of the groups before this one, and of all
 #pragma unroll
-        for (int q = 0; q < S; ++q) tot += s_cnt[q][t];
-        count[(size_t)g * NT + t] = tot;
+    for (int q = 0; q < S; ++q) {
+        before += q < grp ? s_cnt[q][t] : 0u;
+        tot += s_cnt[q][t];
     }
+    gpre[(size_t)g * RASTER_WG + threadIdx.x] = before;
+    if (grp == 0) count[(size_t)g * NT + t] = tot;
 }
 
-// Fill: after the per-group counts, every batch of entries is expanded into
-// a compact list of (entry, pixel) fragments in LDS, and the group's lanes
+// Fill: every batch of entries is expanded into a compact list of (entry,
+// pixel) fragments in LDS, and the group's lanes
 // take one fragment each (instead of one entry per wave step, which left most
 // lanes idle: an entry covers a few pixels of the tile).  Slots within a
 // pixel's list come from LDS counters, so records of one group may land in
@@ -444,14 +444,14 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
                                                     const int4 *__restrict__ vscr, int64_t V,
                                                     const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
                                                     uint64_t rec_cap, uint64_t cap,
-                                                    const uint64_t *__restrict__ masks) {
+                                                    const uint64_t *__restrict__ masks,
+                                                    const uint32_t *__restrict__ gpre) {
     using RS = RasterShape<TW, TH>;
     constexpr int NT = RS::NT, NW = RS::NW, S = RS::S;
     static_assert(NT <= 256, "entry and pixel indices are packed in 8 bits each");
     __shared__ KeySetup s_key[S][NT];
     __shared__ uint64_t s_mask[S][NT * NW];
     __shared__ uint32_t s_pos[S][NT];   // per pixel: next slot of the group
-    __shared__ uint32_t s_fb[S][NT];    // per entry: first fragment in the batch
     __shared__ uint32_t s_wsum[S][NW];  // per wave: fragments (scan carry)
     __shared__ uint16_t s_frag[S][FILL_WINDOW];
     __shared__ uint64_t s_first[NT];
@@ -467,28 +467,10 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
     if (grp == 0) s_first[t] = off[(size_t)g * NT + t] - pass_base;
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
-    // sweep 1: this group's fragments per pixel, from the coverage masks
-    uint32_t n = 0;
-    for (int it = 0; it < ch.iters; ++it) {
-        const uint64_t base = ch.c0 + (uint64_t)it * NT;
-        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
-        if (t < m) {
-#pragma unroll
-            for (int w = 0; w < NW; ++w) s_mask[grp][t * NW + w] = masks[(base + t) * NW + w];
-        }
-        __syncthreads();
-        for (int j = 0; j < m; ++j) n += (uint32_t)((s_mask[grp][j * NW + wave] >> lane) & 1ull);
-        __syncthreads();
-    }
-    s_pos[grp][t] = n;
+    // the group's first slot per pixel (the fragments of the groups before it, from the count pass)
+    s_pos[grp][t] = gpre[(size_t)g * RASTER_WG + threadIdx.x];
     __syncthreads();
-    {  // the group's first slot per pixel: the fragments of the groups before it
-        uint32_t k = 0;
-        for (int q = 0; q < grp; ++q) k += s_pos[q][t];
-        __syncthreads();
-        s_pos[grp][t] = k;
-    }
-    // sweep 2: expand each batch into fragments, one lane per fragment
+    // expand each batch into fragments, one lane per fragment
     for (int it = 0; it < ch.iters; ++it) {
         const uint64_t base = ch.c0 + (uint64_t)it * NT;
         const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
@@ -786,9 +768,10 @@ void launch_tri_bin_scatter(const int4 *face_c, int64_t F, int nv, const int4 *v
     if (tl.TW == TWv && tl.TH == THv) { CALL; return; }
 
 void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, hipStream_t s) {
+                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, uint32_t *gpre,
+                  hipStream_t s) {
     dim3 g((unsigned)((int64_t)tl.ntiles * nv));
-#define ARGS tl, tile_off, bins, face_c, vscr, V, count, cap, masks
+#define ARGS tl, tile_off, bins, face_c, vscr, V, count, cap, masks, gpre
     HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));
@@ -798,10 +781,10 @@ void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint
 
 void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
                  uint64_t cap, const int4 *face_c, const int4 *vscr, int64_t V, const uint64_t *off, uint64_t *rec,
-                 uint64_t rec_cap, const uint64_t *masks, hipStream_t s) {
+                 uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
     if (g1 <= g0) return;
     dim3 g((unsigned)(g1 - g0));
-#define ARGS tl, g0, tile_off, bins, face_c, vscr, V, off, rec, rec_cap, cap, masks
+#define ARGS tl, g0, tile_off, bins, face_c, vscr, V, off, rec, rec_cap, cap, masks, gpre
     HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));

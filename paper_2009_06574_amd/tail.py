@@ -202,7 +202,11 @@ def evaluate_view(r: Renderer, cam, hot, st, params, K=8, conf_mins=(0.5,), reps
     base = baselines(r, hot, st, K, exact)
     rgb = slice(0, 3)
     stats = r.frame_stats()
+    rows = r.learned_features(hot, st, K)
+    eps = 2.0 ** -20
+    head_opaque = float(((1 - rows["head"][:, 3]) < eps).float().mean()) if rows["head"].shape[0] else 0.0
     out = dict(ms_exact=t_exact, long_pixels=sum(stats["classes"][1:7]), fragments=stats["fragments"],
+               head_opaque_frac=head_opaque,
                psnr_truncated=psnr(base["truncated"][..., rgb], exact[..., rgb]),
                psnr_proxy=psnr(base["proxy"][..., rgb], exact[..., rgb]), learned={})
     for cm in conf_mins:
