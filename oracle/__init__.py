@@ -69,6 +69,9 @@ def _load():
     lib.orc_num_threads.restype = ct.c_int
     lib.orc_frame_tail.argtypes = [P, P, P, ct.c_int, ct.c_double, ct.c_double, P, P, P, P]
     lib.orc_frame_tail.restype = ct.c_int
+    lib.orc_frame_approx.argtypes = [P, P, P, ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_double,
+                                     ct.c_double, P]
+    lib.orc_frame_approx.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -101,6 +104,12 @@ def smoothstep(e0, e1, x) -> float:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+# moment-based transparency: bias towards the reference moments and the
+# weight of the bound at the fragment's own depth (readings of the method)
+MBOIT_BETA = 5e-5
+MBOIT_ETA = 0.25
 
 
 class OracleError(RuntimeError):
@@ -223,6 +232,20 @@ class Frame:
         if rc != 0:
             raise OracleError(f"orc_frame_tail failed: {rc}")
         return head, feat, target, has.astype(bool)
+
+    def approx(self, hotspot, style, method, param=4, w0=0.0, w1=1.0, beta=MBOIT_BETA, eta=MBOIT_ETA):
+        """Approximate order-independent resolve per sample pixel (definitions in
+        hexfc_oracle.c): method "mlab" (param = k layers) or "mboit" (four power
+        moments).  Returns rgba [npix, 4] over the background."""
+        hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
+        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        rgba = np.zeros((self.npix, 4))
+        m = {"mlab": 1, "mboit": 2}[method]
+        rc = _load().orc_frame_approx(self._h, _ptr(hv), _ptr(sv), m, int(param), float(beta), float(eta),
+                                      float(w0), float(w1), _ptr(rgba))
+        if rc != 0:
+            raise OracleError(f"orc_frame_approx failed: {rc}")
+        return rgba
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -785,3 +785,179 @@ int orc_frame_tail(orc_frame *fr, const double *hot, const double *st, int K, do
     }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------- approximate resolves
+ * Two order-independent approximations of the sorted blend, on the same
+ * fragment lists (the paper's future work names approximate transparency
+ * without per-pixel sorting; these are the published non-learned methods):
+ *
+ * method 1, multi-layer alpha blending (Salvi and Vaidyanathan, 2014):
+ *   k blending nodes (premultiplied colour, transmittance, depth key) per
+ *   pixel, kept in depth order.  Fragments arrive in primitive order
+ *   (ascending triangle id); each is inserted at its depth (after nodes of
+ *   equal depth); when k+1 nodes exist the last two merge:
+ *   (c, T) = (c_a + T_a c_b, T_a T_b), depth of the front one.  The nodes are
+ *   then blended front to back.  With k >= n this is the exact blend.
+ *
+ * method 2, moment-based order-independent transparency (Muenstermann,
+ *   Krumpen, Klein, Peters, 2018) with four power moments:
+ *   absorbance a_i = -ln(1 - alpha_i) (alpha clamped to 1 - 1e-6), warped
+ *   depth x_i = 2 clamp((w_i - w0) / (w1 - w0), 0, 1) - 1, moments
+ *   b_j = sum a_i x_i^j (j = 0..4).  For each fragment the absorbance in
+ *   front of it is b_0 F(x_i), F from the 4-moment (Hamburger) bound: the
+ *   normalised moments m_j = b_j / b_0, blended towards (0, 0.375, 0, 0.375)
+ *   by beta, are matched by a distribution on three points {x, z2, z3}; z2,
+ *   z3 are the roots of P(t) / (t - x) where P is the monic cubic with
+ *   E[P(X)] = E[X P(X)] = 0 and P(x) = 0; weights by Lagrange
+ *   interpolation; F = (weight of the support points in front of x)
+ *   + eta * (weight at x).  Then C = sum T_i alpha_i c_i with
+ *   T_i = exp(-b_0 F(x_i)), rescaled so that the total opacity is the exact
+ *   1 - exp(-b_0).
+ */
+typedef struct { double c[3], T; int64_t z; } mlab_node;
+
+static void mlab_resolve(const double *fc, const double *fa, const int64_t *fz, int64_t n, int k, double *out) {
+    mlab_node nd[9];
+    int cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        mlab_node x;
+        for (int a = 0; a < 3; ++a) x.c[a] = fc[3 * i + a];
+        x.T = 1.0 - fa[i];
+        x.z = fz[i];
+        int p = cnt;
+        while (p > 0 && nd[p - 1].z > x.z) --p;  /* after nodes of equal depth */
+        for (int q = cnt; q > p; --q) nd[q] = nd[q - 1];
+        nd[p] = x;
+        ++cnt;
+        if (cnt > k) {  /* merge the last two */
+            mlab_node *a = &nd[cnt - 2], *b = &nd[cnt - 1];
+            for (int c = 0; c < 3; ++c) a->c[c] += a->T * b->c[c];
+            a->T *= b->T;
+            --cnt;
+        }
+    }
+    double C[3] = {0, 0, 0}, T = 1.0;
+    for (int q = 0; q < cnt; ++q) {
+        for (int a = 0; a < 3; ++a) C[a] += T * nd[q].c[a];
+        T *= nd[q].T;
+    }
+    for (int a = 0; a < 3; ++a) out[a] = C[a];
+    out[3] = 1.0 - T;
+}
+
+/* fraction of the total absorbance in front of x, from normalised moments m[1..4] */
+static double moment_bound(const double *m, double x, double eta) {
+    /* P(t) = t^3 + p2 t^2 + p1 t + p0 with E[P] = 0, E[X P] = 0, P(x) = 0 */
+    double A[3][4] = {{1.0, m[1], m[2], -m[3]}, {m[1], m[2], m[3], -m[4]}, {1.0, x, x * x, -x * x * x}};
+    for (int c = 0; c < 3; ++c) {  /* Gaussian elimination with partial pivoting */
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c)
+            for (int q = 0; q < 4; ++q) { double t = A[c][q]; A[c][q] = A[piv][q]; A[piv][q] = t; }
+        if (A[c][c] == 0.0) return eta;  /* degenerate: no information */
+        for (int r = c + 1; r < 3; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int q = c; q < 4; ++q) A[r][q] -= f * A[c][q];
+        }
+    }
+    double p[3];
+    for (int c = 2; c >= 0; --c) {
+        double s = A[c][3];
+        for (int q = c + 1; q < 3; ++q) s -= A[c][q] * p[q];
+        p[c] = s / A[c][c];
+    }
+    /* P(t) / (t - x) = t^2 + (p2 + x) t + (p1 + x (p2 + x)) */
+    double bq = p[2] + x, cq = p[1] + x * bq;
+    double disc = bq * bq - 4.0 * cq;
+    if (disc < 0.0) disc = 0.0;
+    double sq = sqrt(disc);
+    double z2 = 0.5 * (-bq - sq), z3 = 0.5 * (-bq + sq);
+    /* weights by Lagrange interpolation: w_k = E[prod_{l != k} (X - x_l) / (x_k - x_l)] */
+    double d2 = (z2 - x) * (z2 - z3), d3 = (z3 - x) * (z3 - z2);
+    double w2 = d2 != 0.0 ? (m[2] - m[1] * (x + z3) + x * z3) / d2 : 0.0;
+    double w3 = d3 != 0.0 ? (m[2] - m[1] * (x + z2) + x * z2) / d3 : 0.0;
+    double w1 = 1.0 - w2 - w3;
+    double F = (z2 < x ? w2 : 0.0) + (z3 < x ? w3 : 0.0) + eta * w1;
+    if (F < 0.0) F = 0.0;
+    if (F > 1.0) F = 1.0;
+    return F;
+}
+
+static void mboit_resolve(const double *fc, const double *fa, const double *fx, int64_t n, double beta, double eta,
+                          double *out) {
+    double b[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        double al = fa[i] < 1.0 - 1e-6 ? fa[i] : 1.0 - 1e-6;
+        double a = -log1p(-al), xp = 1.0;
+        for (int j = 0; j < 5; ++j) { b[j] += a * xp; xp *= fx[i]; }
+    }
+    for (int a = 0; a < 4; ++a) out[a] = 0.0;
+    if (!(b[0] > 0.0)) return;
+    const double ref[5] = {1.0, 0.0, 0.375, 0.0, 0.375};
+    double m[5];
+    for (int j = 0; j < 5; ++j) m[j] = (1.0 - beta) * (b[j] / b[0]) + beta * ref[j];
+    double C[3] = {0, 0, 0}, W = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double T = exp(-b[0] * moment_bound(m, fx[i], eta));
+        for (int a = 0; a < 3; ++a) C[a] += T * fc[3 * i + a];
+        W += T * fa[i];
+    }
+    double A = -expm1(-b[0]);
+    double s = W > 0.0 ? A / W : 0.0;
+    for (int a = 0; a < 3; ++a) out[a] = C[a] * s;
+    out[3] = A;
+}
+
+static int cmp_tri(const void *a, const void *b) {
+    uint32_t x = (uint32_t)(*(const uint64_t *)a & 0xffffffffu), y = (uint32_t)(*(const uint64_t *)b & 0xffffffffu);
+    return x < y ? -1 : x > y;
+}
+
+/* method 1: param = k (1..8); method 2: beta, eta (param unused).  rgba: final
+ * colour over the background, as orc_frame_shade. */
+int orc_frame_approx(orc_frame *fr, const double *hot, const double *st, int method, int param, double beta,
+                     double eta, double w0, double w1, double *rgba) {
+    if (!(hot[3] > 0.0) || (method != 1 && method != 2) || (method == 1 && (param < 1 || param > 8)) ||
+        !(w1 > w0))
+        return ORC_EINVAL;
+    const double *bg = st + ST_BG;
+    int err = 0;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < fr->npix; ++s) {
+        int64_t n = fr->count[s];
+        int64_t i = fr->pix[s] % fr->W, j = fr->pix[s] / fr->W;
+        double out[4] = {0, 0, 0, 0};
+        if (n > 0) {
+            uint64_t *r = (uint64_t *)malloc(sizeof(uint64_t) * n);
+            double *fc = (double *)malloc(sizeof(double) * 3 * n), *fa = (double *)malloc(sizeof(double) * n);
+            double *fx = (double *)malloc(sizeof(double) * n);
+            int64_t *fz = (int64_t *)malloc(sizeof(int64_t) * n);
+            if (!r || !fc || !fa || !fx || !fz) {
+                #pragma omp atomic write
+                err = 1;
+            } else {
+                memcpy(r, fr->rec + fr->off[s], sizeof(uint64_t) * n);
+                if (method == 1) qsort(r, (size_t)n, sizeof(uint64_t), cmp_tri);  /* primitive order */
+                for (int64_t q = 0; q < n; ++q) {
+                    frag f;
+                    shade(fr, i, j, r[q] & 0xffffffffu, hot, st, 0, &f, NULL);
+                    for (int a = 0; a < 3; ++a) fc[3 * q + a] = f.c[a];
+                    fa[q] = f.a;
+                    fz[q] = (int64_t)(r[q] >> 32);
+                    double w = 1048576.0 / (double)(ORC_KMAX - (int64_t)(r[q] >> 32));
+                    double z = (w - w0) / (w1 - w0);
+                    if (z < 0.0) z = 0.0;
+                    if (z > 1.0) z = 1.0;
+                    fx[q] = 2.0 * z - 1.0;
+                }
+                if (method == 1) mlab_resolve(fc, fa, fz, n, param, out);
+                else mboit_resolve(fc, fa, fx, n, beta, eta, out);
+            }
+            free(r); free(fc); free(fa); free(fx); free(fz);
+        }
+        for (int a = 0; a < 3; ++a) rgba[4 * s + a] = out[a] + (1.0 - out[3]) * bg[a];
+        rgba[4 * s + 3] = out[3];
+    }
+    return err ? ORC_ENOMEM : ORC_OK;
+}
