@@ -99,6 +99,9 @@ def learned_tail(r, mesh, conf_min, seeds=range(1001, 1005)):
                 fallback_frac=round(float(np.sum([x["fallback_pixels"] for x in L]) /
                                           max(1, np.sum([d["long_pixels"] for d in res]))), 4),
                 head_opaque_frac=round(float(np.mean([d["head_opaque_frac"] for d in res])), 4),
+                approx_baselines={k: dict(psnr_db=round(float(np.mean([d["approx"][k]["psnr"] for d in res])), 2),
+                                          resolve_ms=round(float(np.mean([d["approx"][k]["ms"] for d in res])), 4))
+                                  for k in res[0]["approx"]},
                 psnr_db_k_truncation=round(float(np.mean([d["psnr_truncated"] for d in res])), 2),
                 psnr_db_proxy_tail=round(float(np.mean([d["psnr_proxy"] for d in res])), 2))
 

@@ -219,6 +219,31 @@ hexfc_status hexfc_get_total_fragments(hexfc_ctx *ctx, uint64_t *out);
 hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uint64_t *off_out,
                                        uint64_t *rec_out, void *stream);
 
+/* Approximate order-independent resolves of the lists of the last
+ * hexfc_build_fragment_lists (one view), for comparison with the exact sorted
+ * blend (the paper names approximate transparency without per-pixel sorting
+ * as future work, Section 7).  Every fragment is shaded by Eq. 1-4.
+ *   HEXFC_APPROX_MLAB     multi-layer alpha blending (Salvi and
+ *                         Vaidyanathan 2014) with k blending nodes (1..8);
+ *                         fragments arrive in primitive order (ascending
+ *                         triangle id), are inserted at their depth (after
+ *                         nodes of equal depth), and the last two nodes merge
+ *                         when there are k + 1.  Exact when k >= list length.
+ *   HEXFC_APPROX_MOMENTS  moment-based order-independent transparency
+ *                         (Muenstermann et al. 2018): four power moments of
+ *                         the absorbance -ln(1 - alpha) over the depth warped
+ *                         to [-1, 1] (clip w over the mesh bbox range); per
+ *                         fragment the Hamburger bound of the absorbance in
+ *                         front (moment bias 5e-5 towards (0, 0.375, 0,
+ *                         0.375), own-depth weight 0.25), in FP64; colours
+ *                         rescaled so that the opacity is the exact
+ *                         1 - prod(1 - alpha).  k is ignored.
+ *   rgba_out              device float [H][W][4] (as hexfc_resolve)
+ * Errors: ESTATE, EINVAL (method), ERANGE (k), EOVERFLOW. */
+enum { HEXFC_APPROX_MLAB = 1, HEXFC_APPROX_MOMENTS = 2 };
+hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                  int method, int k, float *rgba_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned tail compositor.  Long per-pixel lists are resolved as an exact
  * head (the first K fragments in depth order, shaded by Eq. 1-4 and blended

@@ -25,7 +25,7 @@ ABI_SYMBOLS = (
     "hexfc_build_fragment_lists", "hexfc_resolve", "hexfc_render_frame", "hexfc_set_tuning",
     "hexfc_get_frame_stats", "hexfc_get_total_fragments", "hexfc_export_sorted_lists",
     "hexfc_set_profiling", "hexfc_get_kernel_times", "hexfc_render_batch", "hexfc_batch_status",
-    "hexfc_autotune", "hexfc_resolve_learned", "hexfc_learned_features", "hexfc_mlp_param_count",
+    "hexfc_autotune", "hexfc_resolve_approx", "hexfc_resolve_learned", "hexfc_learned_features", "hexfc_mlp_param_count",
     "hexfc_mlp_forward", "hexfc_mlp_loss", "hexfc_mlp_backward", "hexfc_mlp_adam_step",
     "hexfc_status_string", "hexfc_last_error",
 )
@@ -82,6 +82,7 @@ def load():
         "hexfc_render_batch": ([P, ct.c_int, P, P, P, P, P], st),
         "hexfc_batch_status": ([P, P, P, P], st),
         "hexfc_autotune": ([P, ct.c_int, P, P, P, P, ct.c_char_p, P, P], st),
+        "hexfc_resolve_approx": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), ct.c_int, ct.c_int, P, P], st),
         "hexfc_resolve_learned": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), P, ct.c_int, ct.c_float, P, P, P],
                                   st),
         "hexfc_learned_features": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), ct.c_int, P, P, P, P, i64, P, P],
@@ -280,6 +281,18 @@ class Renderer:
 
     KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill") + tuple(
         f"resolve_c{c}" for c in range(8)) + ("tail_features", "mlp_apply", "fallback")
+
+    APPROX_METHODS = {"mlab": 1, "moments": 2}
+
+    def resolve_approx(self, hot, style, method="mlab", k=4, out=None):
+        """Approximate order-independent resolve of the last built lists:
+        "mlab" (k blending layers) or "moments" (four power moments)."""
+        if out is None:
+            out = self.torch.empty((self.H, self.W, 4), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hexfc_resolve_approx(self.ctx, ct.byref(hotspot_struct(hot)),
+                                                  ct.byref(style_struct(style)), self.APPROX_METHODS[method],
+                                                  int(k), _ptr(out), self._stream()))
+        return out
 
     # ------------------------------------------------------------ learned tail
     def learned_features(self, hot, style, K: int = 8, with_target: bool = False) -> dict:

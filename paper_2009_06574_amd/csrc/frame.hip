@@ -313,6 +313,27 @@ hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
     return HEXFC_OK;
 }
 
+hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style, int method,
+                                  int k, float *rgba_out, void *stream) {
+    if (!ctx) return HEXFC_EINVAL;
+    if (!ctx->lists_valid || ctx->nv != 1) FAIL(ctx, HEXFC_ESTATE, "no single-view fragment lists built");
+    TRY(check_shading(ctx, hot, style, rgba_out));
+    if (method != HEXFC_APPROX_MLAB && method != HEXFC_APPROX_MOMENTS) FAIL(ctx, HEXFC_EINVAL, "unknown method %d", method);
+    if (method == HEXFC_APPROX_MLAB && (k < 1 || k > 8)) FAIL(ctx, HEXFC_ERANGE, "MLAB layers must be in [1, 8]");
+    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
+        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
+    TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    shade_params(ctx->h_views[0].sp, hot, style);
+    TRY(upload_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, rgba_out);
+    for (int c = 0; c < NCLASS - 1; ++c)
+        launch_resolve_approx(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap,
+                              (uint32_t)ctx->last_stats[ST_CLASS + c], method, k, a, s);
+    HIPCHK(ctx, hipGetLastError());
+    return HEXFC_OK;
+}
+
 hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const hexfc_hotspot *hot,
                                 const hexfc_style *style, float *rgba_out, void *stream) {
     if (!ctx) return HEXFC_EINVAL;

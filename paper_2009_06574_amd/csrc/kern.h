@@ -198,6 +198,12 @@ void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int 
                           float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
                           int64_t out_base, hipStream_t s);
 
+// Approximate order-independent resolves of the pixels of class cls (wave
+// per pixel): method 1 multi-layer alpha blending with k nodes (1..8),
+// method 2 moment-based transparency (four power moments).
+void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, const ResolveArgs &a,
+                           hipStream_t s);
+
 // Learned tail network (learned.hip).  Parameters: FP32 vector of MLP_PARAMS
 // floats: mu[9], inv_sigma[9], W1[9][64], b1[64], W2[64][64], b2[64],
 // W3[64][5], b3[5]; outputs y[5] = tail RGBA + confidence logit.

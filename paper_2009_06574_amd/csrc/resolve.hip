@@ -450,6 +450,257 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     }
 }
 
+// ------------------------------------------------------------------ approximate resolves
+// Order-independent approximations of the sorted blend on the same lists,
+// one wave per pixel, every fragment shaded:
+//  * multi-layer alpha blending: the list is sorted by triangle id (the
+//    primitive order a rasteriser would deliver), then the wave runs the k
+//    blending nodes in lockstep (every lane holds the same nodes) over the
+//    fragments broadcast one at a time; a new fragment is inserted at its
+//    depth (after nodes of equal depth) and the last two nodes merge when
+//    there are k + 1;
+//  * moment-based transparency with four power moments of the absorbance
+//    over the warped depth, and per fragment the Hamburger bound of the
+//    absorbance in front of it (three-point canonical distribution through
+//    the fragment's depth), in FP64.
+constexpr double MOM_BETA = 5e-5, MOM_ETA = 0.25;
+
+__device__ double moment_fraction(const double (&m)[5], double x) {
+    // monic cubic t^3 + p2 t^2 + p1 t + p0 with E[P] = E[X P] = 0 and P(x) = 0
+    double A[3][4] = {{1.0, m[1], m[2], -m[3]}, {m[1], m[2], m[3], -m[4]}, {1.0, x, x * x, -x * x * x}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+#pragma unroll
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double t = A[c][q];
+            A[c][q] = piv == 1 && c == 0 ? A[1][q] : (piv == 2 ? A[2][q] : A[c][q]);
+            if (piv == 1 && c == 0) A[1][q] = t;
+            if (piv == 2) A[2][q] = t;
+        }
+        if (A[c][c] == 0.0) return MOM_ETA;
+#pragma unroll
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = A[r][c] / A[c][c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) A[r][q] -= q >= c ? f * A[c][q] : 0.0;
+        }
+    }
+    const double p2 = A[2][3] / A[2][2];
+    const double p1 = (A[1][3] - A[1][2] * p2) / A[1][1];
+    // the quadratic factor P(t) / (t - x) = t^2 + bq t + cq
+    const double bq = p2 + x, cq = p1 + x * bq;
+    const double sq = sqrt(fmax(bq * bq - 4.0 * cq, 0.0));
+    const double z2 = 0.5 * (-bq - sq), z3 = 0.5 * (-bq + sq);
+    const double d2 = (z2 - x) * (z2 - z3), d3 = (z3 - x) * (z3 - z2);
+    const double w2 = d2 != 0.0 ? (m[2] - m[1] * (x + z3) + x * z3) / d2 : 0.0;
+    const double w3 = d3 != 0.0 ? (m[2] - m[1] * (x + z2) + x * z2) / d3 : 0.0;
+    const double w1 = 1.0 - w2 - w3;
+    const double F = (z2 < x ? w2 : 0.0) + (z3 < x ? w3 : 0.0) + MOM_ETA * w1;
+    return fmin(fmax(F, 0.0), 1.0);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Loads a pixel's records (lane-blocked: lane l holds elements l*R .. l*R+R-1).
+template <int R>
+__device__ __forceinline__ uint32_t load_list(const ResolveArgs &a, uint32_t p, int lane, uint64_t (&v)[R]) {
+    uint32_t n = min(a.count[p], (uint32_t)(64 * R));
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    if (first + n > a.rec_cap) n = 0;
+    const uint64_t *src = a.rec + first;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        v[r] = e < n ? src[e] : ~0ull;
+    }
+    return n;
+}
+
+// Multi-layer alpha blending: one wave per workgroup; the shaded fragments
+// are staged in LDS in primitive order and the wave walks them in lockstep.
+template <int R>
+__global__ void __launch_bounds__(64) k_resolve_mlab(const uint32_t *__restrict__ list, uint32_t npix, int k,
+                                                     ResolveArgs a) {
+    __shared__ float4 s_c[64 * R];   // premultiplied colour, opacity
+    __shared__ uint32_t s_z[64 * R]; // depth field
+    const int lane = threadIdx.x;
+    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x);
+    if (wave >= npix) return;
+    const uint32_t p = list[wave];
+    uint64_t v[R];
+    const uint32_t n = load_list<R>(a, p, lane, v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = (v[r] << 32) | (v[r] >> 32);  // triangle id first: primitive order
+    bitonic_sort<R>(v, lane);
+    const PixelRef pr = pixel_ref(a.tl, p);
+    const ShadeParams &sp = a.views[pr.view].sp;
+    const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        if (e < n) {
+            const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(v[r] >> 32), pr.x, pr.y);
+            s_c[e] = make_float4(fr.r, fr.g, fr.b, fr.a);
+            s_z[e] = (uint32_t)(v[r] & 0xffffffffu);
+        }
+    }
+    __syncthreads();
+    // up to k + 1 <= 9 nodes, identical on every lane
+    float nc0[9], nc1[9], nc2[9], nT[9];
+    uint32_t nz[9];
+    int cnt = 0;
+    for (uint32_t e = 0; e < n; ++e) {
+        const float4 x = s_c[e];
+        const uint32_t xz = s_z[e];
+        int pos = 0;  // after the nodes of equal or smaller depth
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pos += (q < cnt && nz[q] <= xz) ? 1 : 0;
+#pragma unroll
+        for (int q = 8; q > 0; --q)
+            if (q > pos && q <= cnt) {
+                nc0[q] = nc0[q - 1];
+                nc1[q] = nc1[q - 1];
+                nc2[q] = nc2[q - 1];
+                nT[q] = nT[q - 1];
+                nz[q] = nz[q - 1];
+            }
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            if (q == pos) {
+                nc0[q] = x.x;
+                nc1[q] = x.y;
+                nc2[q] = x.z;
+                nT[q] = 1.f - x.w;
+                nz[q] = xz;
+            }
+        ++cnt;
+        if (cnt > k) {  // merge the last two nodes
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q == cnt - 2) {
+                    nc0[q] += nT[q] * nc0[q + 1];
+                    nc1[q] += nT[q] * nc1[q + 1];
+                    nc2[q] += nT[q] * nc2[q + 1];
+                    nT[q] *= nT[q + 1];
+                }
+            --cnt;
+        }
+    }
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < cnt) {
+            C0 += T * nc0[q];
+            C1 += T * nc1[q];
+            C2 += T * nc2[q];
+            T *= nT[q];
+        }
+    if (lane == 0)
+        reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+            make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], 1.f - T);
+}
+
+// Moment-based transparency: wave per pixel, no sort.
+template <int R>
+__global__ void __launch_bounds__(256) k_resolve_moments(const uint32_t *__restrict__ list, uint32_t npix,
+                                                         ResolveArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (wave >= npix) return;
+    const uint32_t p = list[wave];
+    uint64_t v[R];
+    const uint32_t n = load_list<R>(a, p, lane, v);
+    const PixelRef pr = pixel_ref(a.tl, p);
+    const ViewParams &vp = a.views[pr.view];
+    const ShadeParams &sp = vp.sp;
+    const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    const double zs = 1.0 / ((double)vp.w1 - (double)vp.w0);
+    float fc0[R], fc1[R], fc2[R], fa[R];
+    double xw[R], b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        fc0[r] = fc1[r] = fc2[r] = fa[r] = 0.f;
+        const double w = 1048576.0 / (double)(KMAX - (uint32_t)(v[r] >> 32));
+        xw[r] = 2.0 * fmin(fmax((w - (double)vp.w0) * zs, 0.0), 1.0) - 1.0;
+        if (e < n) {
+            const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(v[r] & 0xffffffffu), pr.x, pr.y);
+            fc0[r] = fr.r;
+            fc1[r] = fr.g;
+            fc2[r] = fr.b;
+            fa[r] = fr.a;
+            const double ab = -log1p(-fmin((double)fr.a, 1.0 - 1e-6));
+            double xp = 1.0;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                b[j] += ab * xp;
+                xp *= xw[r];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) b[j] = wave_sum_d(b[j]);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    if (b[0] > 0.0) {
+        const double ref[5] = {1.0, 0.0, 0.375, 0.0, 0.375};
+        double m[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) m[j] = (1.0 - MOM_BETA) * (b[j] / b[0]) + MOM_BETA * ref[j];
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, W = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (lane * R + r < n) {
+                const double T = exp(-b[0] * moment_fraction(m, xw[r]));
+                c0 += T * fc0[r];
+                c1 += T * fc1[r];
+                c2 += T * fc2[r];
+                W += T * fa[r];
+            }
+        c0 = wave_sum_d(c0);
+        c1 = wave_sum_d(c1);
+        c2 = wave_sum_d(c2);
+        W = wave_sum_d(W);
+        const double At = -expm1(-b[0]);
+        const double sc = W > 0.0 ? At / W : 0.0;
+        C0 = (float)(c0 * sc);
+        C1 = (float)(c1 * sc);
+        C2 = (float)(c2 * sc);
+        A = (float)At;
+    }
+    if (lane == 0) {
+        const float T = 1.f - A;
+        reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+            make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
+    }
+}
+
+void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, const ResolveArgs &a,
+                           hipStream_t s) {
+    if (npix == 0) return;
+#define APPROX(RV)                                                                                    \
+    if (method == 1) k_resolve_mlab<RV><<<dim3(npix), 64, 0, s>>>(pix_list, npix, k, a);              \
+    else k_resolve_moments<RV><<<dim3((npix + 3) / 4), 256, 0, s>>>(pix_list, npix, a);
+    switch (cls) {
+        case 0:
+        case 1: APPROX(1); break;
+        case 2: APPROX(2); break;
+        case 3: APPROX(4); break;
+        case 4: APPROX(8); break;
+        case 5: APPROX(16); break;
+        case 6: APPROX(32); break;
+        default: break;
+    }
+#undef APPROX
+}
+
 void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a, float *head,
                           float *feat, float *target, uint32_t *pix_out, bool rowmajor, int64_t out_base,
                           hipStream_t s) {

@@ -209,6 +209,11 @@ def evaluate_view(r: Renderer, cam, hot, st, params, K=8, conf_mins=(0.5,), reps
                head_opaque_frac=head_opaque,
                psnr_truncated=psnr(base["truncated"][..., rgb], exact[..., rgb]),
                psnr_proxy=psnr(base["proxy"][..., rgb], exact[..., rgb]), learned={})
+    # non-learned order-independent approximations on the same lists
+    out["approx"] = {}
+    for name, method, kk in (("mlab4", "mlab", 4), ("mlab8", "mlab", 8), ("moments", "moments", 0)):
+        t_a = time_call(lambda: r.resolve_approx(hot, st, method, kk, out=learned), reps)
+        out["approx"][name] = dict(psnr=psnr(learned[..., rgb], exact[..., rgb]), ms=t_a)
     for cm in conf_mins:
         t_l = time_call(lambda: r.resolve_learned(hot, st, params, K, cm, out=learned, mask=mask), reps)
         r.batch_status()
