@@ -68,7 +68,7 @@ struct hexfc_ctx {
     uint64_t *ws = nullptr;
     size_t ws_bytes = 0;
     // per-frame scratch, sized for `nv_cap` views
-    hexfc::DevBuf vert_b, vscr, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
+    hexfc::DevBuf vert_b, vscr, fscr, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
         stats;
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists

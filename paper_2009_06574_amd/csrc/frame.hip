@@ -108,6 +108,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
     if (np >= (int64_t(1) << 31))  // pixel ids are 32-bit (PIX_SKIP reserved)
         FAIL(ctx, HEXFC_ERANGE, "%lld padded pixels in the batch exceed 2^31", (long long)np);
     TRY(grow(ctx, ctx->vscr, sizeof(int4) * ctx->V * nv));
+    TRY(grow(ctx, ctx->fscr, sizeof(int4) * 4 * std::max<int64_t>(ctx->F, 1) * nv));
     if (nv > 1) {
         const void *old = ctx->vert_b.p;
         TRY(grow(ctx, ctx->vert_b, sizeof(VertRec) * ctx->V * nv));
@@ -157,19 +158,20 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_COUNT);
-        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), s);
+        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(), s);
         launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>(), nt, ctx->tile_off.as<uint64_t>(),
                             ctx->scan_tmp.as<uint64_t>(), stats + ST_BINS, s);
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_SCATTER);
-        launch_tri_bin_scatter(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_off.as<uint64_t>(),
+        launch_tri_bin_scatter(ctx->fscr.as<int4>(), ctx->F, nv, tl, ctx->tile_off.as<uint64_t>(),
                                ctx->tile_fill.as<uint32_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, s);
     }
     {
         ScopedTimer tm(ctx, s, KID_COUNT);
-        launch_count(tl, nv, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, fc, vscr, ctx->V,
-                     ctx->count.as<uint32_t>(), ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
+        launch_count(tl, nv, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
+                     ctx->fscr.as<int4>(), ctx->F, ctx->count.as<uint32_t>(), ctx->masks.as<uint64_t>(),
+                     ctx->gpre.as<uint32_t>(), s);
     }
     {
         ScopedTimer tm(ctx, s, KID_SCAN);
@@ -270,8 +272,8 @@ void launch_classes(hexfc_ctx *ctx, const ResolveArgs &a, const uint64_t *cls_co
 void timed_fill(hexfc_ctx *ctx, int64_t g0, int64_t g1, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_FILL);
     launch_fill(ctx->tl, g0, g1, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
-                ctx->face_c.as<int4>(), ctx->vscr.as<int4>(), ctx->V, ctx->off.as<uint64_t>(), ctx->ws,
-                ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
+                ctx->fscr.as<int4>(), ctx->F, ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8,
+                ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
 }
 
 }  // namespace
@@ -431,8 +433,8 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
     if (e == hipSuccess) {
         enqueue_front(ctx, n, ctx->tl, cs, false);
         launch_fill(ctx->tl, 0, (int64_t)ctx->tl.ntiles * n, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(),
-                    ctx->bin_cap, ctx->face_c.as<int4>(), ctx->vscr.as<int4>(), ctx->V, ctx->off.as<uint64_t>(),
-                    ctx->ws, ctx->ws_bytes / 8, ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), cs);
+                    ctx->bin_cap, ctx->fscr.as<int4>(), ctx->F, ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8,
+                    ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), cs);
         ResolveArgs a = resolve_args(ctx, rgba_out);
         launch_classes(ctx, a, nullptr, ctx->stats.as<uint64_t>() + ST_CLASS, cs);
         e = hipStreamEndCapture(cs, &g.graph);

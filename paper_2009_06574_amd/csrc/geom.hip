@@ -99,15 +99,32 @@ template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t F, int64_t NVF,
                                                  const int4 *__restrict__ vscr, int64_t V, Tiling tl,
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
-                                                 uint32_t *__restrict__ bins, uint64_t cap) {
+                                                 uint32_t *__restrict__ bins, uint64_t cap,
+                                                 int4 *__restrict__ fscr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t view = i < NVF ? i / F : 0, f = i - view * F;
     int r0[4] = {0, -1, 0, -1}, r1[4] = {0, -1, 0, -1};  // tile ranges of triangles 0 and 1: x0, x1, y0, y1
     bool ok0 = false, ok1 = false;
     if (i < NVF) {
-        const int4 c = face_c[f];
-        const int4 *vs = vscr + view * V;
-        const int4 p0 = vs[c.x], p1 = vs[c.y], p2 = vs[c.z], p3 = vs[c.w];
+        int4 p0, p1, p2, p3;
+        int4 *fs = fscr + 4 * i;  // (view, face) record of the four screen vertices
+        if (SCATTER) {  // the count pass stored them
+            p0 = fs[0];
+            p1 = fs[1];
+            p2 = fs[2];
+            p3 = fs[3];
+        } else {
+            const int4 c = face_c[f];
+            const int4 *vs = vscr + view * V;
+            p0 = vs[c.x];
+            p1 = vs[c.y];
+            p2 = vs[c.z];
+            p3 = vs[c.w];
+            fs[0] = p0;
+            fs[1] = p1;
+            fs[2] = p2;
+            fs[3] = p3;
+        }
         ok0 = tri_tile_range(p0, p1, p2, tl, r0[0], r0[1], r0[2], r0[3]);
         ok1 = tri_tile_range(p0, p2, p3, tl, r1[0], r1[1], r1[2], r1[3]);
     }
@@ -190,13 +207,11 @@ struct KeySetup {
 };
 
 template <bool WITH_KEY>
-__device__ __forceinline__ void tri_setup(const int4 *__restrict__ face_c, const int4 *__restrict__ vscr,
-                                          uint32_t tri, int ox, int oy, int ex, int ey, CovSetup &cs,
-                                          KeySetup &ks) {
-    int4 c = face_c[tri >> 1];
-    int ia, ib, ic;
-    tri_ids(c, (int)(tri & 1), ia, ib, ic);
-    int4 v[3] = {vscr[ia], vscr[ib], vscr[ic]};
+__device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_t tri, int ox, int oy, int ex,
+                                          int ey, CovSetup &cs, KeySetup &ks) {
+    const int4 *fs = fscr + 4 * (size_t)(tri >> 1);  // the face's four screen vertices
+    const int t1 = (int)(tri & 1);
+    int4 v[3] = {fs[0], fs[1 + t1], fs[2 + t1]};
     cs.pad0 = cs.pad1 = cs.pad2 = 0;
     long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
                      (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
@@ -328,8 +343,7 @@ constexpr int RASTER_WINDOW = 1024;  // pairs / fragments expanded at a time per
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
                                                      const uint32_t *__restrict__ bins,
-                                                     const int4 *__restrict__ face_c,
-                                                     const int4 *__restrict__ vscr, int64_t V,
+                                                     const int4 *__restrict__ fscr, int64_t F,
                                                      uint32_t *__restrict__ count, uint64_t cap,
                                                      uint64_t *__restrict__ masks, uint32_t *__restrict__ gpre) {
     using RS = RasterShape<TW, TH>;
@@ -344,7 +358,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
     const int64_t g = blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
-    vscr += view * V;
+    fscr += view * 4 * F;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
@@ -361,7 +375,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
         int box = 0;
         if (t < m) {
             CovSetup cs;
-            tri_setup<false>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, dummy);
+            tri_setup<false>(fscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, dummy);
             s_cov[grp][t] = cs;
             c = (uint32_t)cs.pad1;
             box = cs.pad0;
@@ -440,8 +454,7 @@ constexpr int FILL_WINDOW = RASTER_WINDOW;
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
                                                     const uint32_t *__restrict__ bins,
-                                                    const int4 *__restrict__ face_c,
-                                                    const int4 *__restrict__ vscr, int64_t V,
+                                                    const int4 *__restrict__ fscr, int64_t F,
                                                     const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
                                                     uint64_t rec_cap, uint64_t cap,
                                                     const uint64_t *__restrict__ masks,
@@ -459,7 +472,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
     const int64_t g = g0 + blockIdx.x;  // global tile
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
-    vscr += view * V;
+    fscr += view * 4 * F;
     const int tx = tile % tl.ntx, ty = tile / tl.ntx;
     const int lane = t & 63, wave = t >> 6;
     const int ox = SUB * (tx * TW) + SUB / 2, oy = SUB * (ty * TH) + SUB / 2;
@@ -485,7 +498,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
             if (c) {
                 CovSetup cs;
                 KeySetup ks;
-                tri_setup<true>(face_c, vscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
+                tri_setup<true>(fscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
                 s_key[grp][t] = ks;
             }
         }
@@ -749,29 +762,28 @@ void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *vie
     if (n > 0) k_transform<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(posq, V, n, views, W, H, vert, vscr);
 }
 void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, hipStream_t s) {
+                          uint32_t *tile_cnt, int4 *fscr, hipStream_t s) {
     const int64_t n = F * nv;
     if (n > 0)
         k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_cnt,
-                                                                          nullptr, nullptr, 0);
+                                                                          nullptr, nullptr, 0, fscr);
 }
-void launch_tri_bin_scatter(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
-                            hipStream_t s) {
+void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
+                            uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap, hipStream_t s) {
     const int64_t n = F * nv;
     if (n > 0)
-        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_fill,
-                                                                         tile_off, bins, bin_cap);
+        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(nullptr, F, n, nullptr, 0, tl, tile_fill,
+                                                                         tile_off, bins, bin_cap,
+                                                                         const_cast<int4 *>(fscr));
 }
 
 #define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \
     if (tl.TW == TWv && tl.TH == THv) { CALL; return; }
 
 void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, uint32_t *gpre,
-                  hipStream_t s) {
+                  const int4 *fscr, int64_t F, uint32_t *count, uint64_t *masks, uint32_t *gpre, hipStream_t s) {
     dim3 g((unsigned)((int64_t)tl.ntiles * nv));
-#define ARGS tl, tile_off, bins, face_c, vscr, V, count, cap, masks, gpre
+#define ARGS tl, tile_off, bins, fscr, F, count, cap, masks, gpre
     HEXFC_TILE_DISPATCH(8, 8, (k_count<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 8, (k_count<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 16, (k_count<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));
@@ -780,11 +792,11 @@ void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint
 }
 
 void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *face_c, const int4 *vscr, int64_t V, const uint64_t *off, uint64_t *rec,
+                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec,
                  uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
     if (g1 <= g0) return;
     dim3 g((unsigned)(g1 - g0));
-#define ARGS tl, g0, tile_off, bins, face_c, vscr, V, off, rec, rec_cap, cap, masks, gpre
+#define ARGS tl, g0, tile_off, bins, fscr, F, off, rec, rec_cap, cap, masks, gpre
     HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));

@@ -136,23 +136,23 @@ __device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
 // ---------------------------------------------------------------- launchers (geom.hip)
 void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *views, int W, int H, VertRec *vert,
                       int4 *vscr, hipStream_t s);
+// fscr: per (view, face) the four screen vertices (4 int4), written by the
+// binning count pass and read by the scatter, count and fill passes.
 void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, hipStream_t s);
-void launch_tri_bin_scatter(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                            const uint64_t *tile_off, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
-                            hipStream_t s);
+                          uint32_t *tile_cnt, int4 *fscr, hipStream_t s);
+void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
+                            uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap, hipStream_t s);
 // Count and fill run 512-lane workgroups per tile.  masks: per bin entry and
 // wave, the 64-bit coverage mask; gpre: per tile, RASTER_WG entries (group of
 // the workgroup, pixel) with the fragments of the groups before it.  Both are
 // written by count and read by fill.
 constexpr int RASTER_WG = 512;
 void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
-                  const int4 *face_c, const int4 *vscr, int64_t V, uint32_t *count, uint64_t *masks, uint32_t *gpre,
-                  hipStream_t s);
+                  const int4 *fscr, int64_t F, uint32_t *count, uint64_t *masks, uint32_t *gpre, hipStream_t s);
 // fill global tiles [g0, g1); records are relative to off[g0 * TP]; at most rec_cap records
 void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *face_c, const int4 *vscr, int64_t V, const uint64_t *off, uint64_t *rec,
-                 uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s);
+                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec, uint64_t rec_cap,
+                 const uint64_t *masks, const uint32_t *gpre, hipStream_t s);
 // exclusive scan of n uint32 values into n+1 uint64 values (out[n] = total);
 // `stat` (nullable) receives the total.  tmp: scan_tmp_elems(n) uint64s.
 size_t scan_tmp_elems(int64_t n);
