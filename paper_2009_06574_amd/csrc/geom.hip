@@ -338,7 +338,7 @@ __device__ __forceinline__ Chunk bin_chunk(uint64_t b0, uint64_t b1, int grp) {
 // pixel) pairs -- the pixels of the tile inside the triangle's bounding box
 // -- one lane per pair; LDS atomics accumulate the per-pixel counts and the
 // entries' coverage masks.
-constexpr int RASTER_WINDOW = 1024;  // pairs / fragments expanded at a time per group
+constexpr int RASTER_WINDOW = 1024;  // candidate pairs expanded at a time per group
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *__restrict__ tile_off,
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
 // lanes idle: an entry covers a few pixels of the tile).  Slots within a
 // pixel's list come from LDS counters, so records of one group may land in
 // any order within the group's range; every consumer sorts the list.
-constexpr int FILL_WINDOW = RASTER_WINDOW;
+constexpr int FILL_WINDOW = 512;  // fragments expanded at a time per group (fewer than candidates: LDS for occupancy)
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
