@@ -82,11 +82,19 @@ def _ptr(a):
 
 def style_vector(st) -> np.ndarray:
     """Pack a synth.Style (or anything with the same attributes) into the
-    oracle's 20-double style vector."""
+    oracle's 22-double style vector."""
     v = [float(getattr(st, k)) for k in STYLE_FIELDS]
     v += [float(x) for x in st.tf_rgb_lo] + [float(x) for x in st.tf_rgb_hi]
     v += [float(st.tf_a_lo), float(st.tf_a_hi)] + [float(x) for x in st.bg]
+    v += [float(getattr(st, "lens_mode", 0)), float(getattr(st, "desaturate", 0.0))]
     return np.asarray(v, dtype=np.float64)
+
+
+def _style(st) -> np.ndarray:
+    v = np.ascontiguousarray(style_vector(st) if not isinstance(st, np.ndarray) else st, np.float64)
+    if v.shape != (22,):
+        raise ValueError("a style vector has 22 entries (see style_vector)")
+    return v
 
 
 def hotspot_vector(h) -> np.ndarray:
@@ -197,9 +205,8 @@ class Frame:
         returns (rgba [npix,4], ncand [npix], cand_off [npix+1], cand [n,4])."""
         lib = _load()
         hv = hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot
-        sv = style_vector(style) if not isinstance(style, np.ndarray) else style
+        sv = _style(style)
         hv = np.ascontiguousarray(hv, np.float64)
-        sv = np.ascontiguousarray(sv, np.float64)
         rgba = np.zeros((self.npix, 4))
         ncand = np.zeros(self.npix, np.int32)
         rc = lib.orc_frame_shade(self._h, _ptr(hv), _ptr(sv), _ptr(rgba), _ptr(ncand))
@@ -213,7 +220,7 @@ class Frame:
 
     def shade_one(self, i, j, tri, hotspot, style, flip=0):
         hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
-        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        sv = _style(style)
         out = np.zeros(5)
         _load().orc_shade_one(self._h, int(i), int(j), int(tri), _ptr(hv), _ptr(sv), int(flip), _ptr(out))
         return out
@@ -222,7 +229,7 @@ class Frame:
         """Head composite, tail features and exact tail target per sample pixel
         (learned-tail definition in hexfc_oracle.c): (head, feat, target, has)."""
         hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
-        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        sv = _style(style)
         head = np.zeros((self.npix, 4))
         feat = np.zeros((self.npix, 9))
         target = np.zeros((self.npix, 4))
@@ -238,7 +245,7 @@ class Frame:
         hexfc_oracle.c): method "mlab" (param = k layers) or "mboit" (four power
         moments).  Returns rgba [npix, 4] over the background."""
         hv = np.ascontiguousarray(hotspot_vector(hotspot) if not isinstance(hotspot, np.ndarray) else hotspot)
-        sv = np.ascontiguousarray(style_vector(style) if not isinstance(style, np.ndarray) else style)
+        sv = _style(style)
         rgba = np.zeros((self.npix, 4))
         m = {"mlab": 1, "mboit": 2}[method]
         rc = _load().orc_frame_approx(self._h, _ptr(hv), _ptr(sv), m, int(param), float(beta), float(eta),

@@ -69,7 +69,7 @@ static const int CORNER_NB[8][3] = {
 enum {
     ST_W_BASE, ST_K_FOCUS, ST_HALO_W, ST_HALO_A, ST_DARKEN, ST_S, ST_BRIGHT, ST_DELTA, ST_LOD,
     ST_TF_LO, ST_TF_LO_G, ST_TF_LO_B, ST_TF_HI, ST_TF_HI_G, ST_TF_HI_B, ST_A_LO, ST_A_HI,
-    ST_BG, ST_BG_G, ST_BG_B, ST_COUNT
+    ST_BG, ST_BG_G, ST_BG_B, ST_LENS_MODE, ST_DESAT, ST_COUNT
 };
 
 /* ---------------------------------------------------------------- mesh */
@@ -275,6 +275,8 @@ typedef struct orc_frame {
     const orc_mesh *m;
     int W, H;
     int64_t Mq[16];
+    double wrow[4];    /* row 3 (clip w) of the float camera matrix */
+    double w0, w1;     /* clip-w range of the corners of the mesh bbox */
     int32_t *sx, *sy, *q;
     uint8_t *vflag;
     int64_t npix;
@@ -353,6 +355,25 @@ int orc_frame_raster(const orc_mesh *m, const float *vp, int W, int H, int64_t n
     if (!fr) return ORC_ENOMEM;
     fr->m = m; fr->W = W; fr->H = H;
     for (int i = 0; i < 16; ++i) fr->Mq[i] = (int64_t)rint((double)vp[i] * ORC_MAT_SCALE);
+    for (int i = 0; i < 4; ++i) fr->wrow[i] = (double)vp[12 + i];
+    {   /* view-depth range of the mesh bbox (normalises the depth cue) */
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < m->V; ++v)
+            for (int a = 0; a < 3; ++a) {
+                double x = (double)m->pos_q[3 * v + a] / ORC_POS_SCALE;
+                if (x < lo[a]) lo[a] = x;
+                if (x > hi[a]) hi[a] = x;
+            }
+        fr->w0 = 1e300;
+        fr->w1 = -1e300;
+        for (int c = 0; c < 8; ++c) {
+            double x[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+            double w = fr->wrow[0] * x[0] + fr->wrow[1] * x[1] + fr->wrow[2] * x[2] + fr->wrow[3];
+            if (w < fr->w0) fr->w0 = w;
+            if (w > fr->w1) fr->w1 = w;
+        }
+        if (!(fr->w1 > fr->w0)) fr->w1 = fr->w0 + 1.0;
+    }
     int64_t V = m->V;
     fr->sx = (int32_t *)calloc(V, 4); fr->sy = (int32_t *)calloc(V, 4);
     fr->q = (int32_t *)calloc(V, 4); fr->vflag = (uint8_t *)calloc(V, 1);
@@ -503,9 +524,17 @@ static void shade(const orc_frame *fr, int64_t px_i, int64_t px_j, uint64_t tri,
         for (int a = 0; a < 3; ++a) p[a] += l * (double)m->pos_q[3 * v[i] + a] / ORC_POS_SCALE;
         tf += l * m->t_v[v[i]];
     }
-    /* focus: object-space sphere distance, 0 at the centre, 1 at the border */
-    double dx = p[0] - hot[0], dy = p[1] - hot[1], dz = p[2] - hot[2];
-    double dist = sqrt(dx * dx + dy * dy + dz * dz) / hot[3];
+    /* focus: distance to the lens centre, 0 at the centre, 1 at the border:
+       object-space sphere (lens mode 0) or screen-space circle in pixels
+       (lens mode 1, Section 4: centre hot[0], hot[1], radius hot[3]) */
+    double dist;
+    if (st[ST_LENS_MODE] == 1.0) {
+        double ex = (double)px_i + 0.5 - hot[0], ey = (double)px_j + 0.5 - hot[1];
+        dist = sqrt(ex * ex + ey * ey) / hot[3];
+    } else {
+        double dx = p[0] - hot[0], dy = p[1] - hot[1], dz = p[2] - hot[2];
+        dist = sqrt(dx * dx + dy * dy + dz * dz) / hot[3];
+    }
     double focus = 1.0 - orc_smoothstep(0.7, 1.0, dist);
     /* distances to the four face edges */
     double P[4][3], d[4], L = 0.0;
@@ -598,6 +627,17 @@ static void shade(const orc_frame *fr, int64_t px_i, int64_t px_j, uint64_t tri,
     /* Eq. 4 (premultiplied) */
     for (int a = 0; a < 3; ++a) out->c[a] = aeCe[a] + (1.0 - ae) * afs * Cf[a];
     out->a = ae + (1.0 - ae) * afs;
+    /* depth cue in the focus region: desaturate towards the luminance with
+       the normalised view depth of the fragment */
+    if (st[ST_DESAT] > 0.0) {
+        double w = fr->wrow[0] * p[0] + fr->wrow[1] * p[1] + fr->wrow[2] * p[2] + fr->wrow[3];
+        double z = (w - fr->w0) / (fr->w1 - fr->w0);
+        if (z < 0.0) z = 0.0;
+        if (z > 1.0) z = 1.0;
+        double sd = st[ST_DESAT] * focus * z;
+        double lum = 0.2126 * out->c[0] + 0.7152 * out->c[1] + 0.0722 * out->c[2];
+        for (int a = 0; a < 3; ++a) out->c[a] = (1.0 - sd) * out->c[a] + sd * lum;
+    }
     if (amb) *amb = A;
 }
 

@@ -103,6 +103,8 @@ class Style:
     tf_a_lo: float = 0.05
     tf_a_hi: float = 0.6
     bg: tuple = (0.0, 0.0, 0.0)
+    lens_mode: int = 0          # 0: object-space sphere, 1: screen-space circle (pixels)
+    desaturate: float = 0.0     # depth-cue desaturation strength in the focus region
 
 
 # ----------------------------------------------------------------------------- grids
