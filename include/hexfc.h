@@ -97,6 +97,17 @@ typedef struct hexfc_style {
     float tf_rgb_lo[3], tf_rgb_hi[3];
     float tf_a_lo, tf_a_hi;
     float bg[3];
+    /* lens_mode 0: object-space sphere (hotspot centre and radius in world
+     * units); 1: the screen-space circle of Section 4 (hotspot centre[0],
+     * centre[1] and radius in pixels, pixel (i, j) at (i + 0.5, j + 0.5);
+     * centre[2] unused).  Either way the normalised distance is 1 at the
+     * lens border (focus, Eq. 3). */
+    int32_t lens_mode;
+    /* depth cue in the focus region (Section 8): each fragment's colour is
+     * moved towards its Rec. 709 luminance by desaturate * focus * z, z the
+     * fragment's clip w normalised to the mesh bbox's clip-w range; 0 = off,
+     * at most 1. */
+    float desaturate;
 } hexfc_style;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */

@@ -50,7 +50,8 @@ class CStyle(ct.Structure):
                 ("halo_alpha", ct.c_float), ("darken", ct.c_float), ("accent_s", ct.c_float),
                 ("accent_brighten", ct.c_float), ("delta", ct.c_float), ("lod", ct.c_int32),
                 ("tf_rgb_lo", ct.c_float * 3), ("tf_rgb_hi", ct.c_float * 3),
-                ("tf_a_lo", ct.c_float), ("tf_a_hi", ct.c_float), ("bg", ct.c_float * 3)]
+                ("tf_a_lo", ct.c_float), ("tf_a_hi", ct.c_float), ("bg", ct.c_float * 3),
+                ("lens_mode", ct.c_int32), ("desaturate", ct.c_float)]
 
 
 _lib = None
@@ -127,6 +128,8 @@ def style_struct(s) -> CStyle:
     c.tf_rgb_hi[:] = [float(x) for x in s.tf_rgb_hi]
     c.tf_a_lo, c.tf_a_hi = float(s.tf_a_lo), float(s.tf_a_hi)
     c.bg[:] = [float(x) for x in s.bg]
+    c.lens_mode = int(getattr(s, "lens_mode", 0))
+    c.desaturate = float(getattr(s, "desaturate", 0.0))
     return c
 
 

@@ -30,6 +30,8 @@ hexfc_status check_camera(hexfc_ctx *ctx, const hexfc_camera *cam, Mat3q &M) {
 hexfc_status check_shading(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *sty, const float *rgba) {
     if (!hot || !sty || !rgba) FAIL(ctx, HEXFC_EINVAL, "null hotspot, style or output");
     if (!(hot->radius > 0.f) || !std::isfinite(hot->radius)) FAIL(ctx, HEXFC_EINVAL, "hotspot radius must be > 0");
+    if (sty->lens_mode != 0 && sty->lens_mode != 1) FAIL(ctx, HEXFC_EINVAL, "lens_mode must be 0 or 1");
+    if (!(sty->desaturate >= 0.f && sty->desaturate <= 1.f)) FAIL(ctx, HEXFC_ERANGE, "desaturate must be in [0, 1]");
     return HEXFC_OK;
 }
 
@@ -52,6 +54,8 @@ void shade_params(ShadeParams &p, const hexfc_hotspot *hot, const hexfc_style *s
     }
     p.a_lo = sty->tf_a_lo;
     p.a_hi = sty->tf_a_hi;
+    p.lens_mode = sty->lens_mode;
+    p.desat = sty->desaturate;
 }
 
 // View-depth range [w0, w1] of the mesh bbox: clip w (row 3 of the float
@@ -70,6 +74,9 @@ void depth_range(const hexfc_ctx *ctx, const hexfc_camera *cam, ViewParams &vp) 
     if (!(hi > lo)) hi = lo + 1.0;
     vp.w0 = (float)lo;
     vp.w1 = (float)hi;
+    for (int i = 0; i < 4; ++i) vp.sp.wrow[i] = cam->view_proj[12 + i];
+    vp.sp.zw0 = (float)lo;
+    vp.sp.zinv = (float)(1.0 / (hi - lo));
 }
 
 Tiling make_tiling(const hexfc_ctx *ctx, int W, int H) {
@@ -527,6 +534,8 @@ hexfc_status learned_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexf
     if (!ctx->lists_valid || ctx->nv != 1) FAIL(ctx, HEXFC_ESTATE, "no single-view fragment lists built");
     if (!hot || !style) FAIL(ctx, HEXFC_EINVAL, "null hotspot or style");
     if (!(hot->radius > 0.f) || !std::isfinite(hot->radius)) FAIL(ctx, HEXFC_EINVAL, "hotspot radius must be > 0");
+    if (style->lens_mode != 0)
+        FAIL(ctx, HEXFC_EINVAL, "the learned tail's proxy features are defined for the object-space lens");
     if (K < 1 || K > 64) FAIL(ctx, HEXFC_ERANGE, "K must be in [1, 64]");
     if (ctx->last_stats[ST_CLASS + NCLASS - 1])
         FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);

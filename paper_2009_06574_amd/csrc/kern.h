@@ -66,12 +66,16 @@ struct __align__(16) FaceRec {
     uint32_t lvl, pad0, pad1, pad2;
 };
 
-// Shading constants of one view (hotspot and style).
+// Shading constants of one view (hotspot and style, and for the depth cue
+// the camera's clip-w row with the mesh's clip-w range).
 struct ShadeParams {
     float hc[3], inv_r;
     float w_base, k_focus, halo_w, halo_a, darken, s, bright, delta;
     int lod;
     float lo[3], hi[3], a_lo, a_hi, bg[3];
+    int lens_mode;  // 0: object-space sphere, 1: screen-space circle (pixels)
+    float desat;    // depth-cue desaturation strength
+    float wrow[4], zw0, zinv;
 };
 
 // Everything per view that the kernels read from device memory.

@@ -63,9 +63,16 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
     const float px = l1 * bx + l2 * cx, py = l1 * by + l2 * cy, pz = l1 * bz + l2 * cz;
     const float tb = t1 ? P2.w : P1.w, tc = t1 ? P3.w : P2.w;
     const float tf = l0 * P0.w + l1 * tb + l2 * tc;
-    // focus (object-space sphere)
-    const float hx = (P0.x - sp.hc[0]) + px, hy = (P0.y - sp.hc[1]) + py, hz = (P0.z - sp.hc[2]) + pz;
-    const float dist = sqrtf(hx * hx + hy * hy + hz * hz) * sp.inv_r;
+    // focus: object-space sphere, or the screen-space circle of Section 4
+    // (centre hc[0], hc[1] and radius in pixels)
+    float dist;
+    if (sp.lens_mode == 1) {
+        const float ex = ((float)x + 0.5f) - sp.hc[0], ey = ((float)y + 0.5f) - sp.hc[1];
+        dist = sqrtf(ex * ex + ey * ey) * sp.inv_r;
+    } else {
+        const float hx = (P0.x - sp.hc[0]) + px, hy = (P0.y - sp.hc[1]) + py, hz = (P0.z - sp.hc[2]) + pz;
+        dist = sqrtf(hx * hx + hy * hy + hz * hz) * sp.inv_r;
+    }
     float u = fminf(fmaxf((dist - 0.7f) * (1.0f / 0.3f), 0.f), 1.f);
     const float focus = 1.f - u * u * (3.f - 2.f * u);
     // distances to the four face edges
@@ -110,6 +117,14 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
         const float PF = eF ? (lo + span * tF) * dk : (h ? sp.halo_a : 0.f);
         const float cf = fminf((lo + span * tf) * gain, se != 1.f ? 1.f : INFINITY);
         Ce[ch] = fe * (lo + span * tC) + focus * PF + wf * cf;
+    }
+    if (sp.desat > 0.f) {  // depth cue in the focus region: desaturate with the view depth
+        const float wv = sp.wrow[0] * (P0.x + px) + sp.wrow[1] * (P0.y + py) + sp.wrow[2] * (P0.z + pz) + sp.wrow[3];
+        const float z = fminf(fmaxf((wv - sp.zw0) * sp.zinv, 0.f), 1.f);
+        const float sd = sp.desat * focus * z;
+        const float lum = 0.2126f * Ce[0] + 0.7152f * Ce[1] + 0.0722f * Ce[2];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) Ce[ch] = (1.f - sd) * Ce[ch] + sd * lum;
     }
     o.r = Ce[0];
     o.g = Ce[1];

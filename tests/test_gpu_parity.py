@@ -235,3 +235,39 @@ def test_config2_full_size_sampled(orc):
     mesh, cams, hots, styles = synth.config2()
     r, c = sampled_compare(orc, mesh, cams[0], hots[0], styles[0], ws=8 << 30)
     log(f"[parity] config2 view0 fragments={r.total_fragments()} max list={c.max()} stats={r.frame_stats()}")
+
+
+# ---------------------------------------------------------------- shading variants
+@pytest.mark.parametrize("variant", ["screen_lens", "depth_cue", "screen_lens_depth_cue_white"])
+def test_config0_shading_variants(orc, variant):
+    """The screen-space circular lens, the depth cue in the focus region and
+    the white background (Section 4, Section 8, Section 4.2) against the
+    oracle, whole frame."""
+    mesh, cams, hots, styles = synth.config0()
+    cam = cams[0]
+    st = synth.default_style(cam)
+    hot = hots[0]
+    if "screen_lens" in variant:
+        st.lens_mode = 1
+        hot = synth.Hotspot((140.0, 110.0, 0.0), 60.0)
+    if "depth_cue" in variant:
+        st.desaturate = 0.8
+    if "white" in variant:
+        st.bg = (1.0, 1.0, 1.0)
+    full_compare(orc, mesh, cam, hot, st, label=variant)
+
+
+def test_shading_variant_errors():
+    import paper_2009_06574_amd as hx
+    mesh, cams, hots, styles = synth.config0()
+    r = gpu_renderer(mesh)
+    st = synth.default_style(cams[0], lens_mode=2)
+    with pytest.raises(hx.HexfcError):
+        r.render(cams[0], hots[0], st)
+    st = synth.default_style(cams[0], desaturate=1.5)
+    with pytest.raises(hx.HexfcError):
+        r.render(cams[0], hots[0], st)
+    # the learned tail is defined for the object-space lens only
+    r.build(cams[0])
+    with pytest.raises(hx.HexfcError):
+        r.resolve_learned(hots[0], synth.default_style(cams[0], lens_mode=1), np.zeros(5143, np.float32))
