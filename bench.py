@@ -73,6 +73,47 @@ def measured_traffic(kernel: str):
     return None
 
 
+def batch_views(reps: int = 10):
+    """Batched views in one captured graph: 32 random views (1024x1024, one
+    hotspot each) of the 64^3 jittered mesh, tile shape and sort switch chosen
+    by the autotuner; against the same 32 views rendered one frame at a time."""
+    import torch
+
+    import paper_2009_06574_amd as hx
+    import synth
+    mesh, cams, hots, styles = synth.config3()
+    r = hx.Renderer(0)
+    r.set_workspace(12 << 30)
+    r.upload(mesh)
+    choice = r.autotune(cams, hots, styles)
+    out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        r.render_batch(cams, hots, styles, out=out)
+    frags, overflow = r.batch_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.render_batch(cams, hots, styles, out=out)
+    torch.cuda.synchronize()
+    ms_batch = 1000.0 * (time.perf_counter() - t0) / reps
+    single = torch.empty((cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
+    for i in range(2):
+        r.render(cams[i], hots[i], styles[i], out=single)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, h, st in zip(cams, hots, styles):
+        r.render(c, h, st, out=single)
+    torch.cuda.synchronize()
+    ms_single = 1000.0 * (time.perf_counter() - t0)
+    log(f"[bench] batch of {len(cams)} views: {ms_batch:.2f} ms ({frags / ms_batch / 1e6:.2f} G fragments/s), "
+        f"one at a time {ms_single:.2f} ms, tuning {choice}")
+    return dict(workload=f"64^3 jittered hex grid, {len(cams)} random views at 1024x1024, one graph launch",
+                tuning=dict(tile_w=choice[0], tile_h=choice[1], t_sort=choice[2]),
+                ms_per_batch=round(ms_batch, 3), fragments_per_batch=int(frags), overflow=bool(overflow),
+                fragments_per_s=frags / ms_batch * 1e3, ms_views_one_at_a_time=round(ms_single, 3),
+                speedup_vs_one_at_a_time=round(ms_single / ms_batch, 3))
+
+
 def learned_tail(r, mesh, conf_min, seeds=range(1001, 1005)):
     """Exact vs learned-tail resolve on the same lists: held-out random views
     of the benchmark mesh (the network was trained on seeds 1-1000)."""
@@ -116,6 +157,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=3, help="views timed for the CPU oracle baseline")
     ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-tail resolve comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-views measurement")
     ap.add_argument("--conf-min", type=float, default=0.5, help="learned tail: pixel confidence threshold")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (scale for HBM counters) and exit")
@@ -212,6 +254,12 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_tail(r, mesh, args.conf_min)
+    r.close()
+    r.workspace = None
+    torch.cuda.empty_cache()
+    batch = None
+    if not args.no_batch:
+        batch = batch_views()
 
     cpu = None
     if not args.no_cpu:
@@ -240,6 +288,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned_tail": learned,
+        "batch": batch,
         "detail": {"kernel_ms_per_frame": kernel_ms,
                    "paper_context": "cubic128 (2,097,152 cells) at 1920x1080 on an RTX 2070 SUPER: "
                                     "147.3 ms/frame (45.8 F+C + 101.5 PPFL), other mesh and hardware"},
