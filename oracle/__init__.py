@@ -49,6 +49,7 @@ def _load():
     lib.orc_mesh_free.argtypes = [P]
     lib.orc_mesh_sizes.argtypes = [P, P]
     lib.orc_mesh_export.argtypes = [P, P, P, P, P, P, P]
+    lib.orc_mesh_boundary.argtypes = [P, P]
     lib.orc_scaled_jacobian.argtypes = [P]
     lib.orc_scaled_jacobian.restype = ct.c_double
     lib.orc_smoothstep.argtypes = [ct.c_double, ct.c_double, ct.c_double]
@@ -82,18 +83,19 @@ def _ptr(a):
 
 def style_vector(st) -> np.ndarray:
     """Pack a synth.Style (or anything with the same attributes) into the
-    oracle's 22-double style vector."""
+    oracle's 24-double style vector."""
     v = [float(getattr(st, k)) for k in STYLE_FIELDS]
     v += [float(x) for x in st.tf_rgb_lo] + [float(x) for x in st.tf_rgb_hi]
     v += [float(st.tf_a_lo), float(st.tf_a_hi)] + [float(x) for x in st.bg]
     v += [float(getattr(st, "lens_mode", 0)), float(getattr(st, "desaturate", 0.0))]
+    v += [float(getattr(st, "sil_alpha", 0.0)), float(getattr(st, "sil_tau", 0.02))]
     return np.asarray(v, dtype=np.float64)
 
 
 def _style(st) -> np.ndarray:
     v = np.ascontiguousarray(style_vector(st) if not isinstance(st, np.ndarray) else st, np.float64)
-    if v.shape != (22,):
-        raise ValueError("a style vector has 22 entries (see style_vector)")
+    if v.shape != (24,):
+        raise ValueError("a style vector has 24 entries (see style_vector)")
     return v
 
 
@@ -146,6 +148,12 @@ class Mesh:
     @classmethod
     def from_synth(cls, m):
         return cls(m.xyz, m.hex, m.cell_scalar, m.cell_edge_level)
+
+    def boundary(self):
+        """uint8 [F]: 1 for faces of one cell only (the mesh boundary surface)."""
+        out = np.zeros(self.F, np.uint8)
+        _load().orc_mesh_boundary(self._h, _ptr(out))
+        return out
 
     def export(self):
         V, C, F = self.V, self.C, self.F

@@ -69,7 +69,7 @@ static const int CORNER_NB[8][3] = {
 enum {
     ST_W_BASE, ST_K_FOCUS, ST_HALO_W, ST_HALO_A, ST_DARKEN, ST_S, ST_BRIGHT, ST_DELTA, ST_LOD,
     ST_TF_LO, ST_TF_LO_G, ST_TF_LO_B, ST_TF_HI, ST_TF_HI_G, ST_TF_HI_B, ST_A_LO, ST_A_HI,
-    ST_BG, ST_BG_G, ST_BG_B, ST_LENS_MODE, ST_DESAT, ST_COUNT
+    ST_BG, ST_BG_G, ST_BG_B, ST_LENS_MODE, ST_DESAT, ST_SIL_A, ST_SIL_TAU, ST_COUNT
 };
 
 /* ---------------------------------------------------------------- mesh */
@@ -81,6 +81,7 @@ typedef struct orc_mesh {
     int32_t *face_v;   /* F*4 */
     uint8_t *face_lvl; /* F*4 */
     double *face_te;   /* F*4 */
+    uint8_t *face_bnd; /* F: 1 if the face belongs to one cell only (mesh boundary) */
 } orc_mesh;
 
 typedef struct { int64_t a, b; int lvl; double t; } edge_ent;
@@ -133,7 +134,7 @@ double orc_scaled_jacobian(const double *c) {
 void orc_mesh_free(orc_mesh *m) {
     if (!m) return;
     free(m->pos_q); free(m->t_cell); free(m->t_v);
-    free(m->face_v); free(m->face_lvl); free(m->face_te);
+    free(m->face_v); free(m->face_lvl); free(m->face_te); free(m->face_bnd);
     free(m);
 }
 
@@ -236,14 +237,24 @@ int orc_mesh_build(const float *xyz, int64_t V, const int32_t *hex, int64_t C,
         }
     qsort(Fe, 6 * C, sizeof(face_ent), cmp_face);
     int64_t *first = (int64_t *)malloc(sizeof(int64_t) * (6 * C + 1));
-    int64_t nF = 0;
+    int64_t *single = (int64_t *)malloc(sizeof(int64_t) * (6 * C + 1));  /* first ids of faces of one cell */
+    int64_t nF = 0, nS = 0;
     for (int64_t i = 0; i < 6 * C; ++i)
-        if (i == 0 || memcmp(Fe[i].key, Fe[i - 1].key, sizeof Fe[i].key) != 0) first[nF++] = Fe[i].idx;
+        if (i == 0 || memcmp(Fe[i].key, Fe[i - 1].key, sizeof Fe[i].key) != 0) {
+            first[nF++] = Fe[i].idx;
+            if (i + 1 >= 6 * C || memcmp(Fe[i].key, Fe[i + 1].key, sizeof Fe[i].key) != 0) single[nS++] = Fe[i].idx;
+        }
     qsort(first, nF, sizeof(int64_t), cmp_i64);
+    qsort(single, nS, sizeof(int64_t), cmp_i64);
     m->F = nF;
     m->face_v = (int32_t *)malloc(sizeof(int32_t) * 4 * (nF ? nF : 1));
     m->face_lvl = (uint8_t *)malloc(4 * (nF ? nF : 1));
     m->face_te = (double *)malloc(sizeof(double) * 4 * (nF ? nF : 1));
+    m->face_bnd = (uint8_t *)calloc(nF ? nF : 1, 1);
+    for (int64_t f = 0, q = 0; f < nF; ++f) {  /* both lists ascending: merge */
+        while (q < nS && single[q] < first[f]) ++q;
+        m->face_bnd[f] = q < nS && single[q] == first[f];
+    }
     for (int64_t f = 0; f < nF; ++f) {
         int64_t c = first[f] / 6, lf = first[f] % 6;
         for (int i = 0; i < 4; ++i) m->face_v[4 * f + i] = hex[8 * c + FACE_CORNERS[lf][i]];
@@ -253,12 +264,13 @@ int orc_mesh_build(const float *xyz, int64_t V, const int32_t *hex, int64_t C,
             m->face_te[4 * f + k] = E[e].t;
         }
     }
-    free(first); free(Fe); free(E);
+    free(first); free(single); free(Fe); free(E);
     *out = m;
     return ORC_OK;
 }
 
 void orc_mesh_sizes(const orc_mesh *m, int64_t *out3) { out3[0] = m->V; out3[1] = m->C; out3[2] = m->F; }
+void orc_mesh_boundary(const orc_mesh *m, uint8_t *out) { memcpy(out, m->face_bnd, (size_t)m->F); }
 
 void orc_mesh_export(const orc_mesh *m, int32_t *pos_q, double *t_cell, double *t_v,
                      int32_t *face_v, uint8_t *face_lvl, double *face_te) {
@@ -652,6 +664,63 @@ static void blend(const frag *fs, int64_t n, const double *bg, double *rgba) {
     rgba[3] = A;
 }
 
+/* ---------------------------------------------------------------- silhouettes
+ * White exterior and interior screen-space silhouettes (Section 4.2, the
+ * final look): the depth buffer of the mesh boundary surface (per pixel, the
+ * nearest fragment of a face that belongs to one cell only) is searched for
+ * sharp edges.  A pixel is a silhouette pixel when it sees the boundary
+ * surface and a 4-neighbour inside the image sees none (exterior) or sees it
+ * farther than (1 + tau) times its own view depth (interior; view depth
+ * ratio = inverse ratio of the depth keys, tau taken as the FP32 value).
+ * Silhouette pixels get white of opacity sil_a composited on top:
+ * rgb' = (1 - a) rgb + a, A' = a + (1 - a) A.  Needs every pixel of the frame
+ * (sample set = all pixels in row-major order). */
+static int silhouettes(orc_frame *fr, const double *st, double *rgba) {
+    const int64_t W = fr->W, H = fr->H, P = W * H;
+    if (P <= 0 || fr->npix != P) return ORC_EINVAL;
+    for (int64_t s = 0; s < P; ++s)
+        if (fr->pix[s] != s) return ORC_EINVAL;
+    const orc_mesh *m = fr->m;
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);  /* boundary surface key, 0: none */
+    uint8_t *sil = (uint8_t *)calloc((size_t)P, 1);
+    if (!key || !sil) { free(key); free(sil); return ORC_ENOMEM; }
+    for (int64_t s = 0; s < P; ++s) {
+        key[s] = 0;
+        for (uint64_t k = fr->off[s]; k < fr->off[s + 1]; ++k) {  /* sorted: the first boundary fragment is the nearest */
+            uint64_t r = fr->rec[k];
+            if (m->face_bnd[(r & 0xffffffffu) >> 1]) { key[s] = ORC_KMAX - (int64_t)(r >> 32); break; }
+        }
+    }
+    const double tau = (double)(float)st[ST_SIL_TAU];
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t kp = key[y * W + x];
+            if (kp == 0) continue;
+            const int64_t nb[4][2] = {{x - 1, y}, {x + 1, y}, {x, y - 1}, {x, y + 1}};
+            for (int q = 0; q < 4; ++q) {
+                int64_t nx = nb[q][0], ny = nb[q][1];
+                if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+                int64_t kn = key[ny * W + nx];
+                if (kn == 0 || (double)kp > (1.0 + tau) * (double)kn) { sil[y * W + x] = 1; break; }
+            }
+        }
+    const double a = st[ST_SIL_A];
+    for (int64_t s = 0; s < P; ++s) {
+        if (!sil[s]) continue;
+        double *px = rgba + 4 * s;
+        for (int c = 0; c < 3; ++c) px[c] = (1.0 - a) * px[c] + a;
+        px[3] = a + (1.0 - a) * px[3];
+        if (fr->cand_off)
+            for (int64_t c = fr->cand_off[s]; c < fr->cand_off[s + 1]; ++c) {
+                double *q = fr->cand + 4 * c;
+                for (int ch = 0; ch < 3; ++ch) q[ch] = (1.0 - a) * q[ch] + a;
+                q[3] = a + (1.0 - a) * q[3];
+            }
+    }
+    free(key); free(sil);
+    return ORC_OK;
+}
+
 #define ORC_MAX_COMBOS 64
 
 /* Shade + composite every sample pixel.  ncand[s] = 0: unambiguous;
@@ -714,6 +783,7 @@ int orc_frame_shade(orc_frame *fr, const double *hot, const double *st, double *
     for (int64_t s = 0; s < np; ++s)
         if (pc[s]) { memcpy(fr->cand + 4 * fr->cand_off[s], pc[s], sizeof(double) * 4 * ncand[s]); free(pc[s]); }
     free(pc);
+    if (st[ST_SIL_A] > 0.0) return silhouettes(fr, st, rgba);
     return ORC_OK;
 }
 

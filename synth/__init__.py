@@ -105,6 +105,8 @@ class Style:
     bg: tuple = (0.0, 0.0, 0.0)
     lens_mode: int = 0          # 0: object-space sphere, 1: screen-space circle (pixels)
     desaturate: float = 0.0     # depth-cue desaturation strength in the focus region
+    sil_alpha: float = 0.0      # opacity of the white screen-space silhouettes (0: off)
+    sil_tau: float = 0.02       # relative view-depth jump that makes an interior silhouette
 
 
 # ----------------------------------------------------------------------------- grids
