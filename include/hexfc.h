@@ -108,6 +108,14 @@ typedef struct hexfc_style {
      * fragment's clip w normalised to the mesh bbox's clip-w range; 0 = off,
      * at most 1. */
     float desaturate;
+    /* white exterior and interior screen-space silhouettes of the mesh
+     * boundary surface (the faces of one cell only; Section 4.2, final look):
+     * a pixel that sees the boundary surface is a silhouette pixel when a
+     * 4-neighbour inside the image sees none, or sees it more than
+     * (1 + sil_tau) times farther; it gets white of opacity sil_alpha on top
+     * (rgb' = (1 - a) rgb + a, A' = a + (1 - a) A).  sil_alpha = 0: off.
+     * Applied by hexfc_render_frame, hexfc_resolve and hexfc_render_batch. */
+    float sil_alpha, sil_tau;
 } hexfc_style;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */

@@ -51,7 +51,8 @@ class CStyle(ct.Structure):
                 ("accent_brighten", ct.c_float), ("delta", ct.c_float), ("lod", ct.c_int32),
                 ("tf_rgb_lo", ct.c_float * 3), ("tf_rgb_hi", ct.c_float * 3),
                 ("tf_a_lo", ct.c_float), ("tf_a_hi", ct.c_float), ("bg", ct.c_float * 3),
-                ("lens_mode", ct.c_int32), ("desaturate", ct.c_float)]
+                ("lens_mode", ct.c_int32), ("desaturate", ct.c_float),
+                ("sil_alpha", ct.c_float), ("sil_tau", ct.c_float)]
 
 
 _lib = None
@@ -130,6 +131,8 @@ def style_struct(s) -> CStyle:
     c.bg[:] = [float(x) for x in s.bg]
     c.lens_mode = int(getattr(s, "lens_mode", 0))
     c.desaturate = float(getattr(s, "desaturate", 0.0))
+    c.sil_alpha = float(getattr(s, "sil_alpha", 0.0))
+    c.sil_tau = float(getattr(s, "sil_tau", 0.02))
     return c
 
 

@@ -221,11 +221,15 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
         if (x.lo != y.lo) return x.lo < y.lo;
         return x.idx < y.idx;
     });
-    std::vector<int64_t> first;
+    std::vector<int64_t> first, single;  // single: faces of one cell only (the boundary surface)
     first.reserve(fr.size() / 2 + 1);
     for (size_t i = 0; i < fr.size(); ++i)
-        if (i == 0 || fr[i].hi != fr[i - 1].hi || fr[i].lo != fr[i - 1].lo) first.push_back(fr[i].idx);
+        if (i == 0 || fr[i].hi != fr[i - 1].hi || fr[i].lo != fr[i - 1].lo) {
+            first.push_back(fr[i].idx);
+            if (i + 1 == fr.size() || fr[i + 1].hi != fr[i].hi || fr[i + 1].lo != fr[i].lo) single.push_back(fr[i].idx);
+        }
     std::sort(first.begin(), first.end());
+    std::sort(single.begin(), single.end());
     const int64_t F = (int64_t)first.size();
     if (2 * F >= (int64_t(1) << 31)) FAIL(ctx, HEXFC_ERANGE, "too many faces");
     std::vector<FaceRec> frec(std::max<int64_t>(F, 1));
@@ -268,6 +272,15 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
     HIPCHK(ctx, hipMemcpy(ctx->vert0.p, vrec.data(), sizeof(VertRec) * V, hipMemcpyHostToDevice));
     HIPCHK(ctx, ctx->face_c.ensure(sizeof(int4) * std::max<int64_t>(F, 1)));
     HIPCHK(ctx, ctx->face_px.ensure(sizeof(float4) * std::max<int64_t>(F, 1)));
+    HIPCHK(ctx, ctx->face_bnd.ensure(std::max<int64_t>(F, 1)));
+    if (F) {
+        std::vector<uint8_t> bnd(F);
+        for (int64_t f = 0, q = 0; f < F; ++f) {  // both lists ascending
+            while (q < (int64_t)single.size() && single[q] < first[f]) ++q;
+            bnd[f] = q < (int64_t)single.size() && single[q] == first[f];
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->face_bnd.p, bnd.data(), F, hipMemcpyHostToDevice));
+    }
     if (F) {
         std::vector<int4> fc(F);
         std::vector<float4> px(F);  // face centre and mean corner importance (learned-tail proxy)

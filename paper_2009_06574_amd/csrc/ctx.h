@@ -60,7 +60,7 @@ struct hexfc_ctx {
     std::string err;
     // mesh
     int64_t V = 0, C = 0, F = 0;
-    hexfc::DevBuf posq, vert0, face, face_c, face_px;
+    hexfc::DevBuf posq, vert0, face, face_c, face_px, face_bnd;
     double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
     // tuning
     int tw = 8, th = 8, t_sort = 16;
@@ -68,6 +68,7 @@ struct hexfc_ctx {
     uint64_t *ws = nullptr;
     size_t ws_bytes = 0;
     // per-frame scratch, sized for `nv_cap` views
+    hexfc::DevBuf bdepth;  // per pixel: depth key of the nearest boundary-surface fragment
     hexfc::DevBuf vert_b, vscr, fscr, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
         stats;
     hexfc::DevBuf count_rm_tmp;

@@ -32,6 +32,8 @@ hexfc_status check_shading(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
     if (!(hot->radius > 0.f) || !std::isfinite(hot->radius)) FAIL(ctx, HEXFC_EINVAL, "hotspot radius must be > 0");
     if (sty->lens_mode != 0 && sty->lens_mode != 1) FAIL(ctx, HEXFC_EINVAL, "lens_mode must be 0 or 1");
     if (!(sty->desaturate >= 0.f && sty->desaturate <= 1.f)) FAIL(ctx, HEXFC_ERANGE, "desaturate must be in [0, 1]");
+    if (!(sty->sil_alpha >= 0.f && sty->sil_alpha <= 1.f)) FAIL(ctx, HEXFC_ERANGE, "sil_alpha must be in [0, 1]");
+    if (!(sty->sil_tau >= 0.f) || !std::isfinite(sty->sil_tau)) FAIL(ctx, HEXFC_ERANGE, "sil_tau must be >= 0");
     return HEXFC_OK;
 }
 
@@ -56,6 +58,8 @@ void shade_params(ShadeParams &p, const hexfc_hotspot *hot, const hexfc_style *s
     p.a_hi = sty->tf_a_hi;
     p.lens_mode = sty->lens_mode;
     p.desat = sty->desaturate;
+    p.sil_a = sty->sil_alpha;
+    p.sil_tau = sty->sil_tau;
 }
 
 // View-depth range [w0, w1] of the mesh bbox: clip w (row 3 of the float
@@ -130,6 +134,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
     TRY(grow(ctx, ctx->tile_fill, sizeof(uint32_t) * nt));
     TRY(grow(ctx, ctx->tile_off, sizeof(uint64_t) * (nt + 1)));
     TRY(grow(ctx, ctx->count, sizeof(uint32_t) * np));
+    TRY(grow(ctx, ctx->bdepth, sizeof(uint32_t) * np));
     TRY(grow(ctx, ctx->gpre, sizeof(uint32_t) * nt * RASTER_WG));
     TRY(grow(ctx, ctx->off, sizeof(uint64_t) * (np + 1)));
     TRY(grow(ctx, ctx->scan_tmp, sizeof(uint64_t) * std::max(scan_tmp_elems(np), scan_tmp_elems(nt))));
@@ -276,6 +281,17 @@ void launch_classes(hexfc_ctx *ctx, const ResolveArgs &a, const uint64_t *cls_co
     }
 }
 
+// Silhouettes: the boundary depth of the tiles [g0, g1) of the current lists,
+// and the white overlay once every pass has been resolved.
+void boundary_depth(hexfc_ctx *ctx, int64_t g0, int64_t g1, int64_t pass_p0, hipStream_t s) {
+    launch_boundary_depth(ctx->tl, g0, g1, ctx->views.as<ViewParams>(), ctx->count.as<uint32_t>(),
+                          ctx->off.as<uint64_t>(), pass_p0, ctx->ws, ctx->ws_bytes / 8, ctx->face_bnd.as<uint8_t>(),
+                          ctx->bdepth.as<uint32_t>(), s);
+}
+void silhouettes(hexfc_ctx *ctx, int nv, float *rgba, hipStream_t s) {
+    launch_silhouette(ctx->tl, nv, ctx->views.as<ViewParams>(), ctx->bdepth.as<uint32_t>(), rgba, s);
+}
+
 void timed_fill(hexfc_ctx *ctx, int64_t g0, int64_t g1, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_FILL);
     launch_fill(ctx->tl, g0, g1, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
@@ -318,6 +334,10 @@ hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
     TRY(upload_views(ctx, 1, s));
     ResolveArgs a = resolve_args(ctx, rgba_out);
     launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
+    if (style->sil_alpha > 0.f) {
+        boundary_depth(ctx, 0, ctx->tl.ntiles, 0, s);
+        silhouettes(ctx, 1, rgba_out, s);
+    }
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }
@@ -363,9 +383,14 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
     if (S[ST_CLASS + NCLASS - 1]) FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     const int npass = (int)S[ST_NPASS];
     ResolveArgs a = resolve_args(ctx, rgba_out);
+    const bool sil = style->sil_alpha > 0.f;
     if (npass <= 1) {
         timed_fill(ctx, 0, tl.ntiles, s);
         launch_classes(ctx, a, S + ST_CLASS, nullptr, s);
+        if (sil) {
+            boundary_depth(ctx, 0, tl.ntiles, 0, s);
+            silhouettes(ctx, 1, rgba_out, s);
+        }
         HIPCHK(ctx, hipGetLastError());
         ctx->lists_valid = true;
         return HEXFC_OK;
@@ -383,8 +408,11 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
         timed_fill(ctx, t0, t1, s);
         a.pass_p0 = t0 * tl.TW * tl.TH;
         launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
+        if (sil) boundary_depth(ctx, t0, t1, a.pass_p0, s);
         HIPCHK(ctx, hipGetLastError());
     }
+    if (sil) silhouettes(ctx, 1, rgba_out, s);
+    HIPCHK(ctx, hipGetLastError());
     ctx->last_stats[ST_NPASS] = (uint64_t)npass;
     return HEXFC_OK;
 }
@@ -444,6 +472,9 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
                     ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), cs);
         ResolveArgs a = resolve_args(ctx, rgba_out);
         launch_classes(ctx, a, nullptr, ctx->stats.as<uint64_t>() + ST_CLASS, cs);
+        // silhouettes (the kernels skip the views whose sil_alpha is 0)
+        boundary_depth(ctx, 0, (int64_t)ctx->tl.ntiles * n, 0, cs);
+        silhouettes(ctx, n, rgba_out, cs);
         e = hipStreamEndCapture(cs, &g.graph);
     }
     ctx->prof = prof;

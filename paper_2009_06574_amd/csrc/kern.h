@@ -76,6 +76,7 @@ struct ShadeParams {
     int lens_mode;  // 0: object-space sphere, 1: screen-space circle (pixels)
     float desat;    // depth-cue desaturation strength
     float wrow[4], zw0, zinv;
+    float sil_a, sil_tau;  // silhouettes: opacity (0: off), relative depth jump
 };
 
 // Everything per view that the kernels read from device memory.
@@ -201,6 +202,15 @@ constexpr int NFEAT = 9;
 void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a,
                           float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
                           int64_t out_base, hipStream_t s);
+
+// Silhouettes of the boundary surface: per pixel of global tiles [g0, g1)
+// the depth key of its nearest fragment of a boundary face (0: none), for the
+// views whose sil_a > 0; then white on the silhouette pixels of all views.
+void launch_boundary_depth(const Tiling &tl, int64_t g0, int64_t g1, const ViewParams *views, const uint32_t *count,
+                           const uint64_t *off, int64_t pass_p0, const uint64_t *rec, uint64_t rec_cap,
+                           const uint8_t *face_bnd, uint32_t *bdepth, hipStream_t s);
+void launch_silhouette(const Tiling &tl, int nv, const ViewParams *views, const uint32_t *bdepth, float *rgba,
+                       hipStream_t s);
 
 // Approximate order-independent resolves of the pixels of class cls (wave
 // per pixel): method 1 multi-layer alpha blending with k nodes (1..8),

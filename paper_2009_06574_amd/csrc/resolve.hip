@@ -465,6 +465,87 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     }
 }
 
+// ------------------------------------------------------------------ silhouettes
+// White exterior and interior screen-space silhouettes of the mesh boundary
+// surface (the faces of one cell only): its depth buffer is read off the
+// fragment lists (the nearest boundary fragment of each pixel), and a pixel
+// that sees it is a silhouette pixel when a 4-neighbour inside the image sees
+// none or sees it more than (1 + tau) farther (the depth keys are inverse
+// depths, so the test is key_p > (1 + tau) key_n, in FP64).
+__global__ void __launch_bounds__(256) k_boundary_depth(Tiling tl, int64_t p0, int64_t p1,
+                                                        const ViewParams *__restrict__ views,
+                                                        const uint32_t *__restrict__ count,
+                                                        const uint64_t *__restrict__ off, int64_t pass_p0,
+                                                        const uint64_t *__restrict__ rec, uint64_t rec_cap,
+                                                        const uint8_t *__restrict__ face_bnd,
+                                                        uint32_t *__restrict__ bdepth) {
+    const int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= p1) return;
+    const int64_t view = p / ((int64_t)tl.ntiles * tl.TW * tl.TH);
+    if (!(views[view].sp.sil_a > 0.f)) return;
+    uint32_t n = count[p];
+    const uint64_t first = off[p] - off[pass_p0];
+    if (first + n > rec_cap) n = 0;
+    uint64_t best = ~0ull;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint64_t r = rec[first + k];
+        if (r < best && face_bnd[(uint32_t)(r & 0xffffffffu) >> 1]) best = r;
+    }
+    bdepth[p] = best == ~0ull ? 0u : KMAX - (uint32_t)(best >> 32);
+}
+
+__global__ void __launch_bounds__(256) k_silhouette(Tiling tl, int64_t npx, const ViewParams *__restrict__ views,
+                                                    const uint32_t *__restrict__ bdepth, float *__restrict__ rgba) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // row-major over views
+    if (i >= npx) return;
+    const int64_t WH = (int64_t)tl.W * tl.H;
+    const int64_t view = i / WH;
+    const ShadeParams &sp = views[view].sp;
+    const float a = sp.sil_a;
+    if (!(a > 0.f)) return;
+    const int x = (int)((i - view * WH) % tl.W), y = (int)((i - view * WH) / tl.W);
+    const int64_t vbase = view * (int64_t)tl.ntiles * tl.TW * tl.TH;
+    auto tm = [&](int xx, int yy) {
+        return vbase + ((int64_t)(yy / tl.TH) * tl.ntx + xx / tl.TW) * (tl.TW * tl.TH) + (yy % tl.TH) * tl.TW +
+               xx % tl.TW;
+    };
+    const uint32_t kp = bdepth[tm(x, y)];
+    if (kp == 0) return;
+    const double lim = 1.0 + (double)sp.sil_tau;
+    const int nx[4] = {x - 1, x + 1, x, x}, ny[4] = {y, y, y - 1, y + 1};
+    bool sil = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (nx[q] < 0 || ny[q] < 0 || nx[q] >= tl.W || ny[q] >= tl.H) continue;
+        const uint32_t kn = bdepth[tm(nx[q], ny[q])];
+        sil |= kn == 0 || (double)kp > lim * (double)kn;
+    }
+    if (!sil) return;
+    float4 *o = reinterpret_cast<float4 *>(rgba) + i;
+    float4 c = *o;
+    c.x = (1.f - a) * c.x + a;
+    c.y = (1.f - a) * c.y + a;
+    c.z = (1.f - a) * c.z + a;
+    c.w = a + (1.f - a) * c.w;
+    *o = c;
+}
+
+void launch_boundary_depth(const Tiling &tl, int64_t g0, int64_t g1, const ViewParams *views, const uint32_t *count,
+                           const uint64_t *off, int64_t pass_p0, const uint64_t *rec, uint64_t rec_cap,
+                           const uint8_t *face_bnd, uint32_t *bdepth, hipStream_t s) {
+    const int64_t TP = (int64_t)tl.TW * tl.TH, p0 = g0 * TP, p1 = g1 * TP;
+    if (p1 <= p0) return;
+    k_boundary_depth<<<dim3((unsigned)((p1 - p0 + 255) / 256)), 256, 0, s>>>(tl, p0, p1, views, count, off, pass_p0,
+                                                                           rec, rec_cap, face_bnd, bdepth);
+}
+
+void launch_silhouette(const Tiling &tl, int nv, const ViewParams *views, const uint32_t *bdepth, float *rgba,
+                       hipStream_t s) {
+    const int64_t n = (int64_t)nv * tl.W * tl.H;
+    if (n <= 0) return;
+    k_silhouette<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, n, views, bdepth, rgba);
+}
+
 // ------------------------------------------------------------------ approximate resolves
 // Order-independent approximations of the sorted blend on the same lists,
 // one wave per pixel, every fragment shaded:

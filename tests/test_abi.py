@@ -63,4 +63,4 @@ def test_struct_layouts_match_header():
     import paper_2009_06574_amd as hx
     assert ct.sizeof(hx.CCamera) == 16 * 4 + 8
     assert ct.sizeof(hx.CHotspot) == 16
-    assert ct.sizeof(hx.CStyle) == 4 * (8 + 1 + 3 + 3 + 2 + 3 + 2)
+    assert ct.sizeof(hx.CStyle) == 4 * (8 + 1 + 3 + 3 + 2 + 3 + 2 + 2)

@@ -135,3 +135,16 @@ def test_config3_batch_against_oracle(orc):
     # replay with the same views gives the same image
     img2 = r.render_batch(cams, hots, styles).cpu().numpy()
     assert np.array_equal(img, img2)
+
+
+def test_batch_silhouettes_per_view():
+    """Views of one batch with and without silhouettes: each equals its
+    single-view render."""
+    mesh, cams, hots, styles = small_batch(n=6, seed=2)
+    styles = [synth.default_style(c, sil_alpha=(0.6 if k % 2 == 0 else 0.0)) for k, c in enumerate(cams)]
+    r = gpu_renderer(mesh, 1 << 28)
+    ref, frags = singles(r, cams, hots, styles)
+    img = r.render_batch(cams, hots, styles).cpu().numpy()
+    nf, over = r.batch_status()
+    assert not over and nf == frags
+    assert np.array_equal(img, ref)

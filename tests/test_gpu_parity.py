@@ -271,3 +271,50 @@ def test_shading_variant_errors():
     r.build(cams[0])
     with pytest.raises(hx.HexfcError):
         r.resolve_learned(hots[0], synth.default_style(cams[0], lens_mode=1), np.zeros(5143, np.float32))
+
+
+# ---------------------------------------------------------------- silhouettes
+@pytest.mark.parametrize("sil", [(0.7, 0.02), (1.0, 0.0), (0.35, 0.3)])
+def test_config0_silhouettes(orc, sil):
+    """White exterior and interior silhouettes of the boundary surface
+    (Section 4.2) against the oracle, whole frame: which pixels are
+    silhouettes is an integer decision and must agree exactly, the overlay
+    to the RGBA bar."""
+    mesh, cams, hots, styles = synth.config0()
+    st = synth.default_style(cams[0], sil_alpha=sil[0], sil_tau=sil[1], bg=(1.0, 1.0, 1.0))
+    r, ref, img = full_compare(orc, mesh, cams[0], hots[0], st, label=f"silhouettes {sil}")
+    base = r.render(cams[0], hots[0], synth.default_style(cams[0], bg=(1.0, 1.0, 1.0))).cpu().numpy().reshape(-1, 4)
+    changed = np.any(img != base, axis=1)
+    ref0 = orc.render(mesh, cams[0], hots[0], synth.default_style(cams[0], bg=(1.0, 1.0, 1.0)))
+    ref_changed = np.any(np.abs(ref["rgba"] - ref0["rgba"]) > 0, axis=1)
+    log(f"[parity] silhouettes {sil}: {changed.sum()} pixels (oracle {ref_changed.sum()})")
+    assert changed.sum() > 50
+    assert np.array_equal(changed, ref_changed)
+
+
+def test_silhouettes_multipass_and_resolve():
+    """Silhouettes over several screen passes, and after build + resolve,
+    bitwise equal to the one-pass frame."""
+    mesh, cams, hots, styles = synth.scaled_config(16, 320, 200, "jitter", nviews=2)
+    st = synth.default_style(cams[1], sil_alpha=0.8)
+    r = gpu_renderer(mesh, 1 << 28)
+    a = r.render(cams[1], hots[1], st).cpu().numpy()
+    r.build(cams[1])
+    b = r.resolve(hots[1], st).cpu().numpy()
+    assert np.array_equal(a, b)
+    F = r.total_fragments()
+    small = gpu_renderer(mesh, (F * 8) // 5 + 4096)
+    c = small.render(cams[1], hots[1], st).cpu().numpy()
+    assert small.frame_stats()["passes"] >= 5
+    assert np.array_equal(a, c)
+    plain = r.render(cams[1], hots[1], styles[1]).cpu().numpy()
+    assert np.any(plain != a)
+
+
+def test_silhouette_errors():
+    import paper_2009_06574_amd as hx
+    mesh, cams, hots, styles = synth.config0()
+    r = gpu_renderer(mesh)
+    for kw in ({"sil_alpha": 1.5}, {"sil_alpha": -0.1}, {"sil_alpha": 0.5, "sil_tau": -1.0}):
+        with pytest.raises(hx.HexfcError):
+            r.render(cams[0], hots[0], synth.default_style(cams[0], **kw))
