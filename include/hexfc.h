@@ -71,7 +71,7 @@ typedef struct hexfc_camera {
 } hexfc_camera;
 
 /* Focus region: an object-space sphere (the paper's object-space lens,
- * Section 4 / Section 8): dist = |p - center| / radius, focus =
+ * Section 4 / Section 7.1): dist = |p - center| / radius, focus =
  * 1 - smoothstep(0.7, 1, dist).  radius > 0. */
 typedef struct hexfc_hotspot {
     float center[3];
@@ -103,7 +103,7 @@ typedef struct hexfc_style {
      * centre[2] unused).  Either way the normalised distance is 1 at the
      * lens border (focus, Eq. 3). */
     int32_t lens_mode;
-    /* depth cue in the focus region (Section 8): each fragment's colour is
+    /* depth cue in the focus region (Section 7.1): each fragment's colour is
      * moved towards its Rec. 709 luminance by desaturate * focus * z, z the
      * fragment's clip w normalised to the mesh bbox's clip-w range; 0 = off,
      * at most 1. */
@@ -126,7 +126,8 @@ void hexfc_destroy(hexfc_ctx *ctx);
 
 /* Fragment workspace: caller-owned device memory of `bytes` bytes (8 bytes per
  * fragment record).  A frame whose fragments exceed it is rendered in several
- * screen passes (Section 7: subdividing the screen), each of which must fit;
+ * screen passes (the paper assumes the lists fit, Section 6, and meets a
+ * buffer cap at its largest viewport, Section 7, Table 2), each of which must fit;
  * hexfc_build_fragment_lists needs the whole frame to fit.  The pointer must
  * be 256-byte aligned.  Passing NULL/0 detaches the workspace. */
 hexfc_status hexfc_set_workspace(hexfc_ctx *ctx, void *dev_ptr, size_t bytes);
@@ -241,7 +242,7 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
 /* Approximate order-independent resolves of the lists of the last
  * hexfc_build_fragment_lists (one view), for comparison with the exact sorted
  * blend (the paper names approximate transparency without per-pixel sorting
- * as future work, Section 7).  Every fragment is shaded by Eq. 1-4.
+ * as future work, Section 8).  Every fragment is shaded by Eq. 1-4.
  *   HEXFC_APPROX_MLAB     multi-layer alpha blending (Salvi and
  *                         Vaidyanathan 2014) with k blending nodes (1..8);
  *                         fragments arrive in primitive order (ascending
@@ -269,7 +270,7 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
  * front to back as in Section 3) plus a tail predicted by a small MLP from 9
  * features of the remaining n - K fragments.  This follows the paper's
  * future-work direction of approximating order-independent transparency
- * (Section 7); it is not part of the paper's method, whose exact resolve
+ * (Section 8); it is not part of the paper's method, whose exact resolve
  * (hexfc_resolve) stays the reference and the fallback.
  *
  * Tail features of a pixel (fragments i = K+1..n in depth order), with the

@@ -644,7 +644,8 @@ void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t 
 
 // ------------------------------------------------------------------ pass planning
 // Greedy split of the tile sequence into passes whose fragments fit the
-// workspace (screen subdivision, Section 7).  One thread; binary search over
+// workspace (the paper assumes the lists fit, Section 6, and meets a buffer
+// cap at its largest viewport, Section 7, Table 2).  One thread; binary search over
 // the tile prefix sums.
 __global__ void k_plan(int ntiles, int tp, const uint64_t *__restrict__ off, uint64_t budget,
                        uint64_t *__restrict__ stats) {

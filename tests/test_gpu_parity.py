@@ -241,7 +241,7 @@ def test_config2_full_size_sampled(orc):
 @pytest.mark.parametrize("variant", ["screen_lens", "depth_cue", "screen_lens_depth_cue_white"])
 def test_config0_shading_variants(orc, variant):
     """The screen-space circular lens, the depth cue in the focus region and
-    the white background (Section 4, Section 8, Section 4.2) against the
+    the white background (Section 4, Section 7.1, Section 4.1) against the
     oracle, whole frame."""
     mesh, cams, hots, styles = synth.config0()
     cam = cams[0]

@@ -1,7 +1,7 @@
 """Pins of the shading variants the paper describes beside the default
 look: the screen-space circular lens (Section 4: a circle with a centre and
 radius in screen space, focus 1 at the centre and 0 at its border) and the
-depth cue that desaturates far fragments in the focus region (Section 8).
+depth cue that desaturates far fragments in the focus region (Section 7.1).
 
 A column of equal layers seen head-on gives closed forms: with no edges the
 lens only enters through Eq. 3's min(dist, 1)^4; with the lens at half its
