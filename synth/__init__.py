@@ -245,6 +245,83 @@ def box_grid(nx: int, ny: int, nz: int, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 
                 cell_edge_level=np.zeros((ii.size, 12), dtype=np.uint8), name=f"box{nx}x{ny}x{nz}")
 
 
+
+def polygon_prism(k: int, n: int, m: int, twist: float = 0.0, amp: float = 0.0, seed: int = 0) -> Mesh:
+    """A k-gon (radius 0.5, centred at (0.5, 0.5)) split into k quads around its
+    centre, each quad subdivided n x n, extruded over z in [0, 1] in m layers.
+
+    Block i has corners V_i (polygon corner), M_i (midpoint of side V_i V_i+1),
+    the centre O and M_{i-1}; its point (a, b) (0 <= a, b <= n) is the bilinear
+    blend of those corners at (a/n, b/n).  For k != 4 the vertical edges through
+    the centre are singular (k incident cells); the vertical edges at the polygon
+    corners have one incident cell.  Points on the block sides are generated
+    once, from the side's end points, so neighbouring blocks share them exactly.
+
+    twist: each layer is rotated by twist * z radians about the prism axis.
+    amp: every vertex off the mesh boundary is moved by U(-amp, amp)/n per axis
+    (one ``rng.uniform(-amp, amp, size=(V, 3))`` draw).
+    Cells are ordered by layer, then block, then b, then a.  No LoD levels set.
+    """
+    if k < 3 or n < 1 or m < 1:
+        raise ValueError("polygon_prism needs k >= 3, n >= 1, m >= 1")
+    th = 2.0 * np.pi * np.arange(k) / k
+    Vc = np.stack([0.5 * np.cos(th), 0.5 * np.sin(th)], axis=1)
+    Mc = 0.5 * (Vc + np.roll(Vc, -1, axis=0))
+    O = np.zeros(2)
+    keys, pts = {}, []
+
+    def vid(i, a, b):
+        """Canonical id of block i's point (a, b)."""
+        if a == n and b == n:
+            key, p = ("O",), O
+        elif a == n:    # side M_i -> O, shared with block i + 1
+            key, p = ("I", i, b), Mc[i] + (b / n) * (O - Mc[i])
+        elif b == n:    # side M_{i-1} -> O, shared with block i - 1
+            j = (i - 1) % k
+            key, p = ("I", j, a), Mc[j] + (a / n) * (O - Mc[j])
+        elif b == 0:    # polygon side, V_i -> M_i
+            key, p = ("S", i, a), Vc[i] + (a / n) * (Mc[i] - Vc[i])
+        elif a == 0:    # polygon side, V_i -> M_{i-1}
+            j = (i - 1) % k
+            key, p = ("T", i, b), Vc[i] + (b / n) * (Mc[j] - Vc[i])
+        else:
+            u, v = a / n, b / n
+            j = (i - 1) % k
+            key = ("B", i, a, b)
+            p = (1 - u) * (1 - v) * Vc[i] + u * (1 - v) * Mc[i] + u * v * O + (1 - u) * v * Mc[j]
+        if key not in keys:
+            keys[key] = len(pts)
+            pts.append((p, key[0] in ("S", "T")))
+        return keys[key]
+
+    quads = []
+    for i in range(k):
+        for b in range(n):
+            for a in range(n):
+                quads.append((vid(i, a, b), vid(i, a + 1, b), vid(i, a + 1, b + 1), vid(i, a, b + 1)))
+    quads = np.asarray(quads, dtype=np.int64)
+    nv2 = len(pts)
+    p2 = np.array([p for p, _ in pts])
+    side = np.array([s for _, s in pts])
+    z = np.arange(m + 1, dtype=np.float64) / m
+    ang = twist * z
+    ca, sa = np.cos(ang)[:, None], np.sin(ang)[:, None]
+    x = ca * p2[None, :, 0] - sa * p2[None, :, 1]
+    y = sa * p2[None, :, 0] + ca * p2[None, :, 1]
+    xyz = np.stack([0.5 + x, 0.5 + y, np.broadcast_to(z[:, None], x.shape)], axis=2).reshape(-1, 3)
+    if amp > 0.0:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-amp, amp, size=xyz.shape) / n
+        lay = np.repeat(np.arange(m + 1), nv2)
+        bnd = np.tile(side, m + 1) | (lay == 0) | (lay == m)
+        off[bnd] = 0.0
+        xyz = xyz + off
+    L = np.arange(m, dtype=np.int64)[:, None, None]
+    hexes = np.concatenate([quads[None] + nv2 * L, quads[None] + nv2 * (L + 1)], axis=2).reshape(-1, 8)
+    return Mesh(xyz=xyz.astype(np.float32), hex=hexes.astype(np.int32),
+                cell_edge_level=np.zeros((hexes.shape[0], 12), dtype=np.uint8), name=f"prism{k}_{n}x{m}")
+
+
 # ----------------------------------------------------------------------------- cameras
 
 def look_at(eye, target, up) -> np.ndarray:
