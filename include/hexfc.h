@@ -353,6 +353,52 @@ hexfc_status hexfc_mlp_adam_step(float *params, float *m, float *v, const float 
                                  float beta2, float eps, int step, void *stream);
 
 const char *hexfc_status_string(hexfc_status s);
+/* ---------------------------------------------------------------- LoD
+ * Sheet-based level-of-detail hierarchy of the mesh edges (Section 5,
+ * Section 5.1): the preprocessing that produces cell_edge_level for
+ * hexfc_upload_mesh.  Host-only: no context, no device work; safe to call
+ * concurrently on different meshes.
+ *
+ * Hexahedral sheets (cells joined through topologically parallel edges) are
+ * extracted; each sheet's cells form a component.  Pairs of components that
+ * a merge would join along at least one boundary face are classified as
+ * adjacent (no shared cell), hybrid (shared cells and faces between cells of
+ * only one each) or intersecting, and merged in the order: adjacent, hybrid,
+ * intersecting, then the larger Eq. 5 weight (boundary faces made interior
+ * over the two boundary sizes, over the two cell counts; compared exactly),
+ * then the smaller pair of ids (sheets numbered by first appearance, cells in
+ * order and within a cell the directions of local edges 0, 1, 8; merged
+ * components numbered on from there).  The edges of the faces on both
+ * boundaries that a merge makes interior disappear at the current level; the
+ * first merge opens level 1 and a merge whose result has more than twice
+ * the cells of the larger input of the merge that opened the current level
+ * opens the next one.  Merging ends when no pair can be merged; L is the
+ * last level.  e_level = (level of disappearance) - 1, or L if the edge never
+ * disappears; singular edges (on the boundary with other than 2 incident
+ * cells, inside with other than 4) that disappear get L - 1, edges with one
+ * incident cell keep L.
+ *
+ *   hex              host int32 [C][8] corner ids in [0, V), VTK order
+ *   n_threads        host threads to use; <= 0: min(16, hardware threads)
+ *   cell_edge_level  host uint8 [C][12] out, local edge order of
+ *                    hexfc_upload_mesh; may be NULL
+ *   info             optional summary out
+ * C = 0 is valid (nothing written, info zeroed).  Errors: EINVAL (C < 0,
+ * NULL hex, V <= 0, a repeated corner, a face shared by more than two cells),
+ * ERANGE (ids out of range, V >= 2^31, 12 C >= 2^32 - 1, more than 255
+ * levels), ENOMEM.  Outputs are unspecified after an error. */
+typedef struct hexfc_lod_info {
+    int64_t sheets;          /* number of sheets                       */
+    int64_t edges, faces;    /* distinct edges and faces of the mesh    */
+    int64_t singular_edges;
+    int64_t merges[3];       /* adjacent, hybrid, intersecting merges   */
+    int32_t levels;          /* L, the coarsest level                   */
+    int32_t components_left; /* components when merging stopped         */
+} hexfc_lod_info;
+
+hexfc_status hexfc_build_lod(const int32_t *hex, int64_t C, int64_t V, int32_t n_threads,
+                             uint8_t *cell_edge_level, hexfc_lod_info *info);
+
 const char *hexfc_last_error(const hexfc_ctx *ctx);
 
 #ifdef __cplusplus

@@ -27,7 +27,7 @@ ABI_SYMBOLS = (
     "hexfc_set_profiling", "hexfc_get_kernel_times", "hexfc_render_batch", "hexfc_batch_status",
     "hexfc_autotune", "hexfc_resolve_approx", "hexfc_resolve_learned", "hexfc_learned_features", "hexfc_mlp_param_count",
     "hexfc_mlp_forward", "hexfc_mlp_loss", "hexfc_mlp_backward", "hexfc_mlp_adam_step",
-    "hexfc_status_string", "hexfc_last_error",
+    "hexfc_build_lod", "hexfc_status_string", "hexfc_last_error",
 )
 
 
@@ -56,6 +56,12 @@ class CStyle(ct.Structure):
 
 
 _lib = None
+
+
+class CLodInfo(ct.Structure):
+    _fields_ = [("sheets", ct.c_int64), ("edges", ct.c_int64), ("faces", ct.c_int64),
+                ("singular_edges", ct.c_int64), ("merges", ct.c_int64 * 3), ("levels", ct.c_int32),
+                ("components_left", ct.c_int32)]
 
 
 def load():
@@ -94,6 +100,7 @@ def load():
         "hexfc_mlp_loss": ([P, P, i64, ct.c_float, P, P, P], st),
         "hexfc_mlp_backward": ([P, P, P, i64, P, P], st),
         "hexfc_mlp_adam_step": ([P, P, P, P, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_int, P], st),
+        "hexfc_build_lod": ([P, i64, i64, ct.c_int32, P, ct.POINTER(CLodInfo)], st),
         "hexfc_status_string": ([st], ct.c_char_p),
         "hexfc_last_error": ([P], ct.c_char_p),
     }
@@ -425,3 +432,19 @@ def mlp_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps
             raise ValueError("params, m, v and grad must be contiguous float32 CUDA tensors")
     _status(lib.hexfc_mlp_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), float(lr), float(beta1),
                                     float(beta2), float(eps), int(step), _cur_stream(params)))
+
+
+def build_lod(hexes, V: int, n_threads: int = 0):
+    """Sheet-based LoD levels of a hexahedral mesh (host C++ in the library):
+    returns (cell_edge_level uint8 [C, 12], info dict)."""
+    lib = load()
+    h = np.ascontiguousarray(hexes, dtype=np.int32).reshape(-1, 8)
+    out = np.zeros((h.shape[0], 12), dtype=np.uint8)
+    info = CLodInfo()
+    rc = lib.hexfc_build_lod(h.ctypes.data_as(ct.c_void_p), h.shape[0], int(V), int(n_threads),
+                             out.ctypes.data_as(ct.c_void_p), ct.byref(info))
+    if rc != 0:
+        raise HexfcError(rc, "hexfc_build_lod failed")
+    return out, {"sheets": info.sheets, "edges": info.edges, "faces": info.faces,
+                 "singular_edges": info.singular_edges, "merges": list(info.merges),
+                 "levels": info.levels, "components_left": info.components_left}

@@ -1,7 +1,8 @@
 """Build libhexfc.so (gfx950) in-tree with hipcc.
 
 Every HIP translation unit under csrc/ is compiled for gfx950 only; packed
-FP32 instructions are disabled for all device code.
+FP32 instructions are disabled for all device code.  lod.cpp is host-only
+C++ (the LoD preprocessing) and goes into the same library.
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhexfc.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "frame.hip", "geom.hip", "resolve.hip", "learned.hip"]
+SOURCES = ["api.hip", "frame.hip", "geom.hip", "resolve.hip", "learned.hip", "lod.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(os.path.dirname(HERE), "include")]
@@ -36,7 +37,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
