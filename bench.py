@@ -147,6 +147,26 @@ def learned_tail(r, mesh, conf_min, seeds=range(1001, 1005)):
                 psnr_db_proxy_tail=round(float(np.mean([d["psnr_proxy"] for d in res])), 2))
 
 
+def lod_build(mesh, threads: int = 16):
+    """Time the library's sheet-based LoD builder (host C++) on the benchmark
+    mesh; its topology is the 128^3 grid, whose hierarchy is the dyadic one
+    the synthetic levels already hold (checked)."""
+    import numpy as np
+
+    import paper_2009_06574_amd as hx
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        levels, info = hx.build_lod(mesh.hex, mesh.V, threads)
+        ts.append(time.perf_counter() - t0)
+    same = bool(np.array_equal(levels, mesh.cell_edge_level))
+    log(f"[bench] LoD build {min(ts):.2f} s on {threads} threads ({info['sheets']} sheets, "
+        f"{info['levels']} levels, equals the mesh's levels: {same})")
+    return {"seconds": round(min(ts), 3), "threads": threads, "cells": mesh.C, "sheets": info["sheets"],
+            "levels": info["levels"], "merges": info["merges"], "equals_mesh_levels": same,
+            "paper_context": "cubic128 (2,097,152 cells): 23.0 s on a Ryzen 9 3900X (Table 1), other CPU"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +178,7 @@ def main():
     ap.add_argument("--grid", type=int, default=128, help="grid size (128 = the benchmark workload)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-tail resolve comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-views measurement")
+    ap.add_argument("--no-lod", action="store_true", help="skip the LoD-build timing")
     ap.add_argument("--conf-min", type=float, default=0.5, help="learned tail: pixel confidence threshold")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (scale for HBM counters) and exit")
@@ -261,6 +282,8 @@ def main():
     if not args.no_batch:
         batch = batch_views()
 
+    lod = None if args.no_lod else lod_build(mesh)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -289,6 +312,7 @@ def main():
         "cpu_baseline": cpu,
         "learned_tail": learned,
         "batch": batch,
+        "lod_build": lod,
         "detail": {"kernel_ms_per_frame": kernel_ms,
                    "paper_context": "cubic128 (2,097,152 cells) at 1920x1080 on an RTX 2070 SUPER: "
                                     "147.3 ms/frame (45.8 F+C + 101.5 PPFL), other mesh and hardware"},

@@ -318,3 +318,23 @@ def test_silhouette_errors():
     for kw in ({"sil_alpha": 1.5}, {"sil_alpha": -0.1}, {"sil_alpha": 0.5, "sil_tau": -1.0}):
         with pytest.raises(hx.HexfcError):
             r.render(cams[0], hots[0], synth.default_style(cams[0], **kw))
+
+
+# ---------------------------------------------------------------- sheet-based LoD on a non-grid mesh
+@pytest.mark.parametrize("lod_level", [1, 2])
+def test_polygon_prism_with_sheet_lod(orc, lod_level):
+    """A twisted pentagon prism (singular centre edges, sheets that cross and
+    touch) with its edge levels from the library's sheet-based LoD builder
+    (Section 5), rendered whole-frame against the oracle fed the oracle's own
+    levels; the two level sets are first checked equal."""
+    import paper_2009_06574_amd as hx
+    from oracle import lod
+    mesh = synth.polygon_prism(5, 6, 8, twist=0.6, amp=0.05, seed=3)
+    got, info = hx.build_lod(mesh.hex, mesh.V)
+    want, winfo = lod.sheet_lod(mesh.hex)
+    assert np.array_equal(got, want) and info["levels"] == winfo["levels"] >= 2
+    mesh.cell_edge_level = want
+    cam = synth.orbit_camera((0.5, 0.5, 0.5), 2.0, 35.0, 25.0, 256, 224)
+    st = synth.default_style(cam, lod=lod_level)
+    hot = synth.Hotspot((0.55, 0.5, 0.6), 0.3)
+    full_compare(orc, mesh, cam, hot, st, label=f"prism lod={lod_level}")
