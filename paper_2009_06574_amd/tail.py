@@ -11,7 +11,7 @@ holds device buffers, draws minibatch indices and times with events.
 The learned tail is not part of the paper's method: it follows the paper's
 future-work remark on approximating order-independent transparency
 (Section 8), with the exact sort-and-blend resolve as its fallback and as the
-judge of its quality.
+reference its quality is measured against.
 
 Command line (runs on a GPU)::
 
