@@ -69,7 +69,7 @@ struct hexfc_ctx {
     size_t ws_bytes = 0;
     // per-frame scratch, sized for `nv_cap` views
     hexfc::DevBuf bdepth;  // per pixel: depth key of the nearest boundary-surface fragment
-    hexfc::DevBuf vert_b, vscr, fscr, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
+    hexfc::DevBuf vert_b, vscr, fscr, bslot, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
         stats;
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists

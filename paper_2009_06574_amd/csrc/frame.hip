@@ -120,6 +120,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
         FAIL(ctx, HEXFC_ERANGE, "%lld padded pixels in the batch exceed 2^31", (long long)np);
     TRY(grow(ctx, ctx->vscr, sizeof(int4) * ctx->V * nv));
     TRY(grow(ctx, ctx->fscr, sizeof(int4) * 4 * std::max<int64_t>(ctx->F, 1) * nv));
+    TRY(grow(ctx, ctx->bslot, sizeof(uint32_t) * 4 * std::max<int64_t>(ctx->F, 1) * nv));
     if (nv > 1) {
         const void *old = ctx->vert_b.p;
         TRY(grow(ctx, ctx->vert_b, sizeof(VertRec) * ctx->V * nv));
@@ -130,7 +131,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
         ctx->vert_b_views = std::max(ctx->vert_b_views, nv);
     }
     TRY(grow(ctx, ctx->views, sizeof(ViewParams) * nv));
-    TRY(grow(ctx, ctx->tile_cnt, sizeof(uint32_t) * nt));
+    TRY(grow(ctx, ctx->tile_cnt, sizeof(uint32_t) * 2 * nt));
     TRY(grow(ctx, ctx->tile_fill, sizeof(uint32_t) * nt));
     TRY(grow(ctx, ctx->tile_off, sizeof(uint64_t) * (nt + 1)));
     TRY(grow(ctx, ctx->count, sizeof(uint32_t) * np));
@@ -161,7 +162,7 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     int4 *vscr = ctx->vscr.as<int4>();
     const uint64_t budget = ctx->ws ? ctx->ws_bytes / 8 : 0;
     launch_zero_u64(stats, ST_COUNT, s);
-    launch_zero_u32(ctx->tile_cnt.as<uint32_t>(), nt, s);
+    launch_zero_u32(ctx->tile_cnt.as<uint32_t>(), 2 * nt, s);
     launch_zero_u32(ctx->tile_fill.as<uint32_t>(), nt, s);
     {
         ScopedTimer tm(ctx, s, KID_TRANSFORM);
@@ -170,14 +171,16 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_COUNT);
-        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(), s);
-        launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>(), nt, ctx->tile_off.as<uint64_t>(),
+        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(),
+                             ctx->bslot.as<uint32_t>(), s);
+        launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>() + nt, nt, ctx->tile_off.as<uint64_t>(),
                             ctx->scan_tmp.as<uint64_t>(), stats + ST_BINS, s);
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_SCATTER);
         launch_tri_bin_scatter(ctx->fscr.as<int4>(), ctx->F, nv, tl, ctx->tile_off.as<uint64_t>(),
-                               ctx->tile_fill.as<uint32_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap, s);
+                               ctx->tile_cnt.as<uint32_t>(), ctx->tile_fill.as<uint32_t>(), ctx->bins.as<uint32_t>(),
+                               ctx->bin_cap, ctx->bslot.as<uint32_t>(), s);
     }
     {
         ScopedTimer tm(ctx, s, KID_COUNT);

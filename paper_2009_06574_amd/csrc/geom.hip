@@ -95,12 +95,21 @@ __device__ __forceinline__ bool tri_tile_range(const int4 a, const int4 b, const
 // leaders then issue their atomics together, so their latencies overlap.
 // The order of a tile's entries is not fixed; nothing downstream depends on
 // it.
+//
+// The counting pass keeps, for the first BIN_SLOTS tiles of every face, the
+// slot it reserved in the tile (counter `lo`); the scatter pass writes those
+// entries there with no atomic.  A face's further tiles reserve from a second
+// counter (`hi`) and are placed by atomics in the scatter pass, after the
+// tile's `lo` entries.
+constexpr int BIN_SLOTS = 4;
+
 template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t F, int64_t NVF,
                                                  const int4 *__restrict__ vscr, int64_t V, Tiling tl,
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
                                                  uint32_t *__restrict__ bins, uint64_t cap,
-                                                 int4 *__restrict__ fscr) {
+                                                 int4 *__restrict__ fscr, uint32_t *__restrict__ bslot,
+                                                 const uint32_t *__restrict__ tile_lo, int64_t NT) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t view = i < NVF ? i / F : 0, f = i - view * F;
     int r0[4] = {0, -1, 0, -1}, r1[4] = {0, -1, 0, -1};  // tile ranges of triangles 0 and 1: x0, x1, y0, y1
@@ -150,6 +159,17 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
             h1 = ok1 && x >= r1[0] && x <= r1[1] && y >= r1[2] && y <= r1[3];
             if (h0 || h1) tile = tile0 + (int64_t)y * tl.ntx + x;
         }
+        if (SCATTER && k < BIN_SLOTS) {  // (k is the same on every lane)
+            if (tile >= 0) {
+                uint64_t idx = tile_off[tile] + bslot[i * BIN_SLOTS + k];
+                if (h0) {
+                    if (idx < cap) bins[idx] = (uint32_t)(2 * f);
+                    ++idx;
+                }
+                if (h1 && idx < cap) bins[idx] = (uint32_t)(2 * f + 1);
+            }
+            continue;
+        }
         // group the lanes by tile (ballots only), then one atomic per group,
         // all groups' atomics in flight together
         unsigned long long pend = __ballot(tile >= 0);
@@ -168,10 +188,13 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
             pend &= ~__ballot(mine);
         }
         unsigned base = 0;
-        if (tile >= 0 && my_leader == lane) base = atomicAdd(&tile_ctr[tile], lead_count);
+        // count pass: the first slots' counter, or the second one past them
+        uint32_t *ctr = (SCATTER || k < BIN_SLOTS) ? tile_ctr : tile_ctr + NT;
+        if (tile >= 0 && my_leader == lane) base = atomicAdd(&ctr[tile], lead_count);
         base = __shfl(base, my_leader);
+        if (!SCATTER && tile >= 0 && k < BIN_SLOTS) bslot[i * BIN_SLOTS + k] = base + my_rank;
         if (SCATTER && tile >= 0) {
-            uint64_t idx = tile_off[tile] + base + my_rank;
+            uint64_t idx = tile_off[tile] + tile_lo[tile] + base + my_rank;
             if (h0) {
                 if (idx < cap) bins[idx] = (uint32_t)(2 * f);
                 ++idx;
@@ -762,20 +785,28 @@ void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *vie
     const int64_t n = V * nv;
     if (n > 0) k_transform<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(posq, V, n, views, W, H, vert, vscr);
 }
+__global__ void k_tile_totals(uint32_t *__restrict__ ctr, int64_t NT) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < NT) ctr[NT + g] += ctr[g];
+}
+
 void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, int4 *fscr, hipStream_t s) {
-    const int64_t n = F * nv;
+                          uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot, hipStream_t s) {
+    const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
         k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_cnt,
-                                                                          nullptr, nullptr, 0, fscr);
+                                                                          nullptr, nullptr, 0, fscr, bslot, nullptr,
+                                                                          NT);
+    if (NT > 0) k_tile_totals<<<dim3((unsigned)((NT + 255) / 256)), 256, 0, s>>>(tile_cnt, NT);
 }
 void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
-                            uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap, hipStream_t s) {
-    const int64_t n = F * nv;
+                            const uint32_t *tile_lo, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
+                            const uint32_t *bslot, hipStream_t s) {
+    const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
-        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(nullptr, F, n, nullptr, 0, tl, tile_fill,
-                                                                         tile_off, bins, bin_cap,
-                                                                         const_cast<int4 *>(fscr));
+        k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(
+            nullptr, F, n, nullptr, 0, tl, tile_fill, tile_off, bins, bin_cap, const_cast<int4 *>(fscr),
+            const_cast<uint32_t *>(bslot), tile_lo, NT);
 }
 
 #define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \

@@ -143,10 +143,16 @@ void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *vie
                       int4 *vscr, hipStream_t s);
 // fscr: per (view, face) the four screen vertices (4 int4), written by the
 // binning count pass and read by the scatter, count and fill passes.
+// tile_cnt: 2 NT counters (NT = tiles of all views): [0, NT) the entries of
+// the faces' first four tiles, whose slots the count pass stores in bslot
+// (4 u32 per (view, face)); [NT, 2 NT) the other entries, then the tile
+// totals (the scan's input).  The scatter places the first kind from bslot
+// and the others after them with atomics on tile_fill.
 void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, int4 *fscr, hipStream_t s);
+                          uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot, hipStream_t s);
 void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
-                            uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap, hipStream_t s);
+                            const uint32_t *tile_lo, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
+                            const uint32_t *bslot, hipStream_t s);
 // Count and fill run 512-lane workgroups per tile.  masks: per bin entry and
 // wave, the 64-bit coverage mask; gpre: per tile, RASTER_WG entries (group of
 // the workgroup, pixel) with the fragments of the groups before it.  Both are
