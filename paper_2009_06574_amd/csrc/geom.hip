@@ -229,9 +229,8 @@ struct KeySetup {
     unsigned pad;
 };
 
-template <bool WITH_KEY>
 __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_t tri, int ox, int oy, int ex,
-                                          int ey, CovSetup &cs, KeySetup &ks) {
+                                          int ey, CovSetup &cs) {
     const int4 *fs = fscr + 4 * (size_t)(tri >> 1);  // the face's four screen vertices
     const int t1 = (int)(tri & 1);
     int4 v[3] = {fs[0], fs[1 + t1], fs[2 + t1]};
@@ -251,19 +250,12 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
         area = -area;
     }
     int ea[3], eb[3], ec[3];
-    long long n0 = 0, na = 0, nb = 0;
     bool reject = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int4 p = v[k], q = v[(k + 1) % 3];
         int A = p.y - q.y, B = q.x - p.x;  // E(x,y) = A (x - px) + B (y - py)
         long long Eo = (long long)A * (ox - p.x) + (long long)B * (oy - p.y);
-        if (WITH_KEY) {
-            long long qo = v[(k + 2) % 3].z;  // edge k is opposite vertex k+2
-            n0 += Eo * qo;
-            na += (long long)A * qo;
-            nb += (long long)B * qo;
-        }
         bool owned = (A > 0) || (A == 0 && B > 0);  // dy < 0, or dy == 0 and dx > 0
         long long Eb = owned ? Eo : Eo - 1;
         long long ax = (long long)A * ex, by = (long long)B * ey;
@@ -298,15 +290,41 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
         cs.pad0 = x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
         cs.pad1 = (x1 - x0 + 1) * (y1 - y0 + 1);
     }
-    if (WITH_KEY) {
-        ks.n0 = n0;
-        ks.na = na;
-        ks.nb = nb;
-        ks.D = area;
-        ks.rD = 1.0 / (double)area;
-        ks.tri = tri;
-        ks.pad = 0;
+}
+
+// Depth-key setup of a triangle for the fill (its coverage is already known,
+// as masks): oriented like tri_setup, N(dx, dy) = sum over the edges of the
+// edge function times the opposite vertex's q, D = twice the area.
+__device__ __forceinline__ void key_setup(const int4 *__restrict__ fscr, uint32_t tri, int ox, int oy, KeySetup &ks) {
+    const int4 *fs = fscr + 4 * (size_t)(tri >> 1);
+    const int t1 = (int)(tri & 1);
+    int4 v[3] = {fs[0], fs[1 + t1], fs[2 + t1]};
+    long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
+                     (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
+    if (area < 0) {
+        int4 t = v[1];
+        v[1] = v[2];
+        v[2] = t;
+        area = -area;
     }
+    long long n0 = 0, na = 0, nb = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int4 p = v[k], q = v[(k + 1) % 3];
+        const int A = p.y - q.y, B = q.x - p.x;
+        const long long Eo = (long long)A * (ox - p.x) + (long long)B * (oy - p.y);
+        const long long qo = v[(k + 2) % 3].z;  // edge k is opposite vertex k + 2
+        n0 += Eo * qo;
+        na += (long long)A * qo;
+        nb += (long long)B * qo;
+    }
+    ks.n0 = n0;
+    ks.na = na;
+    ks.nb = nb;
+    ks.D = area;
+    ks.rD = 1.0 / (double)area;
+    ks.tri = tri;
+    ks.pad = 0;
 }
 
 __device__ __forceinline__ bool covers(const CovSetup &s, int dx, int dy) {
@@ -341,6 +359,21 @@ struct RasterShape {
     static constexpr int NT = TW * TH, NW = NT / 64, S = RASTER_WG / NT;
     static_assert(NT % 64 == 0 && RASTER_WG % NT == 0, "tile shape");
 };
+
+// Synchronise the lanes of one group (the NT lanes that work on one bin
+// chunk).  A one-wave group only needs its own LDS traffic drained and no
+// code motion across the point: the LDS executes a wave's accesses in order.
+// Wider groups need the workgroup barrier, and then every group of the
+// workgroup must reach the same number of them.
+template <int NW>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (NW == 1) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
 
 // chunk [c0, c1) of the tile's bin range [b0, b1) for group grp of S
 struct Chunk {
@@ -390,7 +423,6 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
     const uint64_t b0 = min(tile_off[g], cap), b1 = min(tile_off[g + 1], cap);
     const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
     s_cnt[grp][t] = 0;
-    KeySetup dummy;
     for (int it = 0; it < ch.iters; ++it) {
         const uint64_t base = ch.c0 + (uint64_t)it * NT;
         const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
@@ -398,7 +430,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
         int box = 0;
         if (t < m) {
             CovSetup cs;
-            tri_setup<false>(fscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, dummy);
+            tri_setup(fscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs);
             s_cov[grp][t] = cs;
             c = (uint32_t)cs.pad1;
             box = cs.pad0;
@@ -412,22 +444,27 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
             if (lane >= o) incl += y;
         }
         if (lane == 63) s_wsum[grp][wave] = incl;
-        __syncthreads();
+        group_sync<NW>();
         uint32_t carry = 0, total = 0, most = 0;
+        if constexpr (NW == 1) {
+            total = s_wsum[grp][0];
+            most = total;  // (a one-wave group runs its own number of windows)
+        } else {
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            uint32_t tq = 0;
+            for (int q = 0; q < S; ++q) {
+                uint32_t tq = 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t ws = s_wsum[q][w];
-                if (q == grp) carry += w < wave ? ws : 0u;
-                tq += ws;
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t ws = s_wsum[q][w];
+                    if (q == grp) carry += w < wave ? ws : 0u;
+                    tq += ws;
+                }
+                if (q == grp) total = tq;
+                most = max(most, tq);
             }
-            if (q == grp) total = tq;
-            most = max(most, tq);
         }
         const uint32_t cb = carry + incl - c;
-        // (every group runs the same number of windows: the loop holds barriers)
+        // (wider groups all run the same number of windows: the loop holds barriers)
         for (uint32_t w0 = 0; w0 < most; w0 += RASTER_WINDOW) {
             if (c && cb < w0 + RASTER_WINDOW && cb + c > w0) {
                 const int x0 = box & 255, x1 = (box >> 8) & 255, y0 = (box >> 16) & 255, y1 = (box >> 24) & 255;
@@ -436,7 +473,7 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
                     for (int xx = x0; xx <= x1 && pos < w0 + RASTER_WINDOW; ++xx, ++pos)
                         if (pos >= w0) s_cand[grp][pos - w0] = (uint16_t)((t << 8) | (yy * TW + xx));
             }
-            __syncthreads();
+            group_sync<NW>();
             const uint32_t nf = w0 < total ? min((uint32_t)RASTER_WINDOW, total - w0) : 0u;
             for (uint32_t f = t; f < nf; f += NT) {
                 const uint32_t pr = s_cand[grp][f];
@@ -447,13 +484,13 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
                     atomicOr(&s_macc[grp][j * NW + (pp >> 6)], 1ull << (pp & 63));
                 }
             }
-            __syncthreads();
+            group_sync<NW>();
         }
         if (t < m) {
 #pragma unroll
             for (int w = 0; w < NW; ++w) masks[(base + t) * NW + w] = s_macc[grp][t * NW + w];
         }
-        __syncthreads();  // s_cov, s_macc and s_wsum are rewritten by the next batch
+        group_sync<NW>();  // s_cov, s_macc and s_wsum are rewritten by the next batch
     }
     __syncthreads();
     uint32_t before = 0, tot = 0;  // fragments of the groups before this one, and of all
@@ -518,10 +555,9 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
                 s_mask[grp][t * NW + w] = mk;
                 c += (uint32_t)__popcll(mk);
             }
-            if (c) {
-                CovSetup cs;
+            if (c) {  // (a covered triangle is not culled: its area is not zero)
                 KeySetup ks;
-                tri_setup<true>(fscr, bins[base + t], ox, oy, SUB * (TW - 1), SUB * (TH - 1), cs, ks);
+                key_setup(fscr, bins[base + t], ox, oy, ks);
                 s_key[grp][t] = ks;
             }
         }
@@ -548,7 +584,9 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
             most = max(most, tq);
         }
         const uint32_t fb = carry + incl - c;
-        // (every group runs the same number of windows: the loop holds barriers)
+        // (every group runs the same number of windows: the loop holds barriers.  Keeping
+        // the groups of a tile in step measured faster here than wave-level
+        // synchronisation: their record stores to the tile's lists meet in the caches.)
         for (uint32_t w0 = 0; w0 < most; w0 += FILL_WINDOW) {
             // entries write their fragments that fall into this window
             if (c && fb < w0 + FILL_WINDOW && fb + c > w0) {
