@@ -172,6 +172,26 @@ def test_ragged_small_viewport(orc):
     full_compare(orc, mesh, cam, hots[0], synth.default_style(cam), label="ragged")
 
 
+def test_maximum_viewport_width(orc):
+    """The largest viewport side the ABI accepts (8192) with a ragged 40-pixel
+    height, whole frame."""
+    mesh, cams, hots, styles = synth.config0()
+    cam = synth.orbit_camera((0.5, 0.5, 0.5), 1.2, 30.0, 20.0, 8192, 40, fovy_deg=60.0)
+    r, ref, img = full_compare(orc, mesh, cam, hots[0], synth.default_style(cam), label="max width")
+    assert (ref["count"] > 0).sum() > 500
+
+
+@pytest.mark.parametrize("size,fovy", [((1000, 8192), 100.0), ((8192, 8192), 45.0)])
+def test_maximum_viewport_sampled(orc, size, fovy):
+    """8192 pixels high (a tall frame needs a wide vertical field of view to
+    keep the camera matrix within the integer contract), and 8192 x 8192
+    (67 M pixels, a million tiles): sampled pixels."""
+    mesh, cams, hots, styles = synth.config0()
+    cam = synth.orbit_camera((0.5, 0.5, 0.5), 2.5, 30.0, 20.0, size[0], size[1], fovy_deg=fovy)
+    r, c = sampled_compare(orc, mesh, cam, hots[0], synth.default_style(cam), ws=1 << 31, nsample=2000)
+    assert (c > 0).mean() > 0.05
+
+
 def test_empty_and_culled(orc):
     mesh, cams, hots, styles = synth.config0()
     st = styles[0]
