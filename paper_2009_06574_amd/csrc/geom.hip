@@ -738,11 +738,16 @@ void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, ui
 }
 
 // ------------------------------------------------------------------ length classes
+// Each block classifies CLS_PPT * 256 consecutive pixels (coalesced rows of
+// 256).  Class counts are aggregated per wave (lanes of one class take one
+// LDS atomic), per block in LDS, and then with one global atomic per class
+// and block: the class counters are the most contended addresses of the frame.
+constexpr int CLS_PPT = 8;
+
 __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t p1,
                                                   const uint32_t *__restrict__ count, int t_sort,
                                                   uint32_t *__restrict__ lists, int64_t cap,
                                                   uint64_t *__restrict__ stats) {
-    // block-level aggregation in LDS, then one global atomic per class and block
     __shared__ unsigned s_n[NCLASS];
     __shared__ unsigned long long s_f[NCLASS], s_base[NCLASS];
     if (threadIdx.x < NCLASS) {
@@ -750,24 +755,51 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
         s_f[threadIdx.x] = 0;
     }
     __syncthreads();
-    const int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int TP = tl.TW * tl.TH;
-    int cls = -1;
-    uint32_t n = 0;
-    if (p < p1) {
-        const int64_t lp = p % ((int64_t)tl.ntiles * TP);  // pixel within its view
-        int tile = (int)(lp / TP), l = (int)(lp % TP);
-        int x = (tile % tl.ntx) * tl.TW + l % tl.TW;
-        int y = (tile / tl.ntx) * tl.TH + l / tl.TW;
-        if (x < tl.W && y < tl.H) {
-            n = count[p];
-            cls = length_class(n, t_sort);
+    const int64_t blk0 = p0 + (int64_t)blockIdx.x * (256 * CLS_PPT);
+    int cls[CLS_PPT];
+    unsigned rank[CLS_PPT];
+    unsigned long long fsum[NCLASS];
+#pragma unroll
+    for (int c = 0; c < NCLASS; ++c) fsum[c] = 0;
+#pragma unroll
+    for (int i = 0; i < CLS_PPT; ++i) {
+        const int64_t p = blk0 + i * 256 + threadIdx.x;
+        cls[i] = -1;
+        rank[i] = 0;
+        if (p < p1) {
+            const int64_t lp = p % ((int64_t)tl.ntiles * TP);  // pixel within its view
+            const int tile = (int)(lp / TP), l = (int)(lp % TP);
+            const int x = (tile % tl.ntx) * tl.TW + l % tl.TW;
+            const int y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+            if (x < tl.W && y < tl.H) {
+                const uint32_t n = count[p];
+                cls[i] = length_class(n, t_sort);
+#pragma unroll
+                for (int c = 0; c < NCLASS; ++c) fsum[c] += cls[i] == c ? n : 0u;
+            }
+        }
+        // one LDS atomic per class present in the wave
+        unsigned long long pend = __ballot(cls[i] >= 0);
+        while (pend) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const int lc = __shfl(cls[i], leader);
+            const unsigned long long m = __ballot(cls[i] == lc);
+            unsigned base = 0;
+            if (lane == leader) base = atomicAdd(&s_n[lc], (unsigned)__popcll(m));
+            base = __shfl(base, leader);
+            if (cls[i] == lc) rank[i] = base + (unsigned)__popcll(m & below);
+            pend &= ~m;
         }
     }
-    unsigned rank = 0;
-    if (cls >= 0) {
-        rank = atomicAdd(&s_n[cls], 1u);
-        atomicAdd(&s_f[cls], (unsigned long long)n);
+#pragma unroll
+    for (int c = 0; c < NCLASS; ++c) {
+        unsigned long long v = fsum[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0 && v) atomicAdd(&s_f[c], v);
     }
     __syncthreads();
     if (threadIdx.x < NCLASS) {
@@ -776,7 +808,9 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
         if (s_f[c]) atomicAdd((unsigned long long *)&stats[ST_CLASSF + c], s_f[c]);
     }
     __syncthreads();
-    if (cls >= 0) lists[(int64_t)cls * cap + s_base[cls] + rank] = (uint32_t)p;
+#pragma unroll
+    for (int i = 0; i < CLS_PPT; ++i)
+        if (cls[i] >= 0) lists[(int64_t)cls[i] * cap + s_base[cls[i]] + rank[i]] = (uint32_t)(blk0 + i * 256 + threadIdx.x);
 }
 
 void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *count, int t_sort,
@@ -785,7 +819,9 @@ void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *c
     int64_t p0 = g0 * TP, p1 = g1 * TP;
     int64_t n = p1 - p0;
     if (n <= 0) return;
-    k_classify<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, p0, p1, count, t_sort, cls_lists, cls_cap, stats);
+    const int64_t per = 256 * CLS_PPT;
+    k_classify<<<dim3((unsigned)((n + per - 1) / per)), 256, 0, s>>>(tl, p0, p1, count, t_sort, cls_lists, cls_cap,
+                                                                     stats);
 }
 
 // ------------------------------------------------------------------ small utilities
