@@ -294,8 +294,49 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
             }
             px[f] = make_float4((float)ctr[0], (float)ctr[1], (float)ctr[2], (float)tbar);
         }
+        // Binning order: the faces along a Morton curve of their centres, so
+        // that the faces of one wave are neighbours on screen as well and
+        // meet few distinct tiles (fewer tile atomics).  Records and every
+        // other face array keep the canonical (first-seen) face ids.
+        std::vector<uint32_t> ord(F);
+        {
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int64_t f = 0; f < F; ++f) {
+                const double c3[3] = {px[f].x, px[f].y, px[f].z};
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], c3[a]);
+                    hi[a] = std::max(hi[a], c3[a]);
+                }
+            }
+            auto spread = [](uint64_t x) {  // 21 bits to every third bit
+                x &= 0x1fffffull;
+                x = (x | (x << 32)) & 0x1f00000000ffffull;
+                x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+                x = (x | (x << 8)) & 0x100f00f00f00f00full;
+                x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+                x = (x | (x << 2)) & 0x1249249249249249ull;
+                return x;
+            };
+            std::vector<uint64_t> code(F);
+            for (int64_t f = 0; f < F; ++f) {
+                const double c3[3] = {px[f].x, px[f].y, px[f].z};
+                uint64_t m = 0;
+                for (int a = 0; a < 3; ++a) {
+                    const double u = (c3[a] - lo[a]) / std::max(hi[a] - lo[a], 1e-30);
+                    m |= spread((uint64_t)std::min(std::max(u * 2097152.0, 0.0), 2097151.0)) << a;
+                }
+                code[f] = m;
+                ord[f] = (uint32_t)f;
+            }
+            std::sort(ord.begin(), ord.end(),
+                      [&](uint32_t x, uint32_t y) { return code[x] != code[y] ? code[x] < code[y] : x < y; });
+        }
+        std::vector<int4> fco(F);
+        for (int64_t i = 0; i < F; ++i) fco[i] = fc[ord[i]];
+        HIPCHK(ctx, ctx->face_ord.ensure(sizeof(uint32_t) * F));
         HIPCHK(ctx, hipMemcpy(ctx->face.p, frec.data(), sizeof(FaceRec) * F, hipMemcpyHostToDevice));
-        HIPCHK(ctx, hipMemcpy(ctx->face_c.p, fc.data(), sizeof(int4) * F, hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(ctx->face_c.p, fco.data(), sizeof(int4) * F, hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(ctx->face_ord.p, ord.data(), sizeof(uint32_t) * F, hipMemcpyHostToDevice));
         HIPCHK(ctx, hipMemcpy(ctx->face_px.p, px.data(), sizeof(float4) * F, hipMemcpyHostToDevice));
     }
     for (int a = 0; a < 3; ++a) {  // bbox of the dequantised positions

@@ -60,7 +60,8 @@ struct hexfc_ctx {
     std::string err;
     // mesh
     int64_t V = 0, C = 0, F = 0;
-    hexfc::DevBuf posq, vert0, face, face_c, face_px, face_bnd;
+    hexfc::DevBuf posq, vert0, face, face_px, face_bnd;
+    hexfc::DevBuf face_c, face_ord;  // binning order: corner ids, and the canonical face id
     double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
     // tuning
     int tw = 8, th = 8, t_sort = 16;

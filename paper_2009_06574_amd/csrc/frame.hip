@@ -171,8 +171,8 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_COUNT);
-        launch_tri_bin_count(fc, ctx->F, nv, vscr, ctx->V, tl, ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(),
-                             ctx->bslot.as<uint32_t>(), s);
+        launch_tri_bin_count(fc, ctx->face_ord.as<uint32_t>(), ctx->F, nv, vscr, ctx->V, tl,
+                             ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(), ctx->bslot.as<uint32_t>(), s);
         launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>() + nt, nt, ctx->tile_off.as<uint64_t>(),
                             ctx->scan_tmp.as<uint64_t>(), stats + ST_BINS, s);
     }
@@ -256,7 +256,6 @@ ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba) {
     a.mesh.posq = ctx->posq.as<int4>();
     a.mesh.vert = vert_ptr(ctx, ctx->nv);
     a.mesh.face = ctx->face.as<FaceRec>();
-    a.mesh.face_c = ctx->face_c.as<int4>();
     a.mesh.vscr = ctx->vscr.as<int4>();
     a.mesh.face_px = ctx->face_px.as<float4>();
     a.mesh.V = ctx->V;

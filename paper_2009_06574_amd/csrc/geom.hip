@@ -104,32 +104,39 @@ __device__ __forceinline__ bool tri_tile_range(const int4 a, const int4 b, const
 constexpr int BIN_SLOTS = 4;
 
 template <bool SCATTER>
-__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c, int64_t F, int64_t NVF,
+__global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c,
+                                                 const uint32_t *__restrict__ face_ord, int64_t F, int64_t NVF,
                                                  const int4 *__restrict__ vscr, int64_t V, Tiling tl,
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
                                                  uint32_t *__restrict__ bins, uint64_t cap,
                                                  int4 *__restrict__ fscr, uint32_t *__restrict__ bslot,
                                                  const uint32_t *__restrict__ tile_lo, int64_t NT) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t view = i < NVF ? i / F : 0, f = i - view * F;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (view, position in binning order)
+    const int64_t view = i < NVF ? i / F : 0, fo = i - view * F;
+    // bin entries name triangles by binning position (2 fo + t): the count and
+    // fill passes then read the screen vertices in binning order too; the fill
+    // takes the canonical face id for the records from the w of corner 0
+    const int64_t f = fo;
     int r0[4] = {0, -1, 0, -1}, r1[4] = {0, -1, 0, -1};  // tile ranges of triangles 0 and 1: x0, x1, y0, y1
     bool ok0 = false, ok1 = false;
     if (i < NVF) {
         int4 p0, p1, p2, p3;
-        int4 *fs = fscr + 4 * i;  // (view, face) record of the four screen vertices
+        int4 *fs = fscr + 4 * i;  // (view, binning position) record of the four screen vertices
         if (SCATTER) {  // the count pass stored them
             p0 = fs[0];
+            p0.w = p0.w < 0;
             p1 = fs[1];
             p2 = fs[2];
             p3 = fs[3];
         } else {
-            const int4 c = face_c[f];
+            const int4 c = face_c[fo];
             const int4 *vs = vscr + view * V;
             p0 = vs[c.x];
             p1 = vs[c.y];
             p2 = vs[c.z];
             p3 = vs[c.w];
-            fs[0] = p0;
+            // corner 0's flag gives way to the canonical face id (-1: culled corner)
+            fs[0] = make_int4(p0.x, p0.y, p0.z, p0.w ? -1 : (int)face_ord[fo]);
             fs[1] = p1;
             fs[2] = p2;
             fs[3] = p3;
@@ -237,7 +244,7 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
     cs.pad0 = cs.pad1 = cs.pad2 = 0;
     long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
                      (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
-    if ((v[0].w | v[1].w | v[2].w) || area == 0) {  // (culled triangles are never binned)
+    if (v[0].w < 0 || (v[1].w | v[2].w) || area == 0) {  // (culled triangles are never binned)
         cs.a0 = cs.b0 = cs.a1 = cs.b1 = cs.a2 = cs.b2 = 0;
         cs.c0 = -1;
         cs.c1 = cs.c2 = 0;
@@ -299,6 +306,7 @@ __device__ __forceinline__ void key_setup(const int4 *__restrict__ fscr, uint32_
     const int4 *fs = fscr + 4 * (size_t)(tri >> 1);
     const int t1 = (int)(tri & 1);
     int4 v[3] = {fs[0], fs[1 + t1], fs[2 + t1]};
+    ks.tri = ((uint32_t)v[0].w << 1) | (uint32_t)t1;  // the canonical triangle id (corner 0's w)
     long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
                      (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
     if (area < 0) {
@@ -323,7 +331,6 @@ __device__ __forceinline__ void key_setup(const int4 *__restrict__ fscr, uint32_
     ks.nb = nb;
     ks.D = area;
     ks.rD = 1.0 / (double)area;
-    ks.tri = tri;
     ks.pad = 0;
 }
 
@@ -864,11 +871,13 @@ __global__ void k_tile_totals(uint32_t *__restrict__ ctr, int64_t NT) {
     if (g < NT) ctr[NT + g] += ctr[g];
 }
 
-void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot, hipStream_t s) {
+void launch_tri_bin_count(const int4 *face_c, const uint32_t *face_ord, int64_t F, int nv, const int4 *vscr,
+                          int64_t V, const Tiling &tl, uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot,
+                          hipStream_t s) {
     const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
-        k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, F, n, vscr, V, tl, tile_cnt,
+        k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, face_ord, F, n, vscr, V, tl,
+                                                                          tile_cnt,
                                                                           nullptr, nullptr, 0, fscr, bslot, nullptr,
                                                                           NT);
     if (NT > 0) k_tile_totals<<<dim3((unsigned)((NT + 255) / 256)), 256, 0, s>>>(tile_cnt, NT);
@@ -879,7 +888,7 @@ void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &t
     const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
         k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(
-            nullptr, F, n, nullptr, 0, tl, tile_fill, tile_off, bins, bin_cap, const_cast<int4 *>(fscr),
+            nullptr, nullptr, F, n, nullptr, 0, tl, tile_fill, tile_off, bins, bin_cap, const_cast<int4 *>(fscr),
             const_cast<uint32_t *>(bslot), tile_lo, NT);
 }
 
@@ -898,8 +907,8 @@ void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint
 }
 
 void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec,
-                 uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
+                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec, uint64_t rec_cap,
+                 const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
     if (g1 <= g0) return;
     dim3 g((unsigned)(g1 - g0));
 #define ARGS tl, g0, tile_off, bins, fscr, F, off, rec, rec_cap, cap, masks, gpre

@@ -96,7 +96,6 @@ struct DevMesh {
     const int4 *posq;      // [V] (X_q, Y_q, Z_q, 0)
     const VertRec *vert;   // [NV*V] world part replicated per view, screen part per view
     const FaceRec *face;   // [F]
-    const int4 *face_c;    // [F] corner ids alone (dense, for the rasteriser)
     const int4 *vscr;      // [NV*V] screen part alone (dense, for the rasteriser)
     const float4 *face_px; // [F] face centre (xyz) and mean corner importance: learned-tail proxy
     int64_t V, F;
@@ -141,15 +140,21 @@ __device__ __forceinline__ int length_class(uint32_t n, int t_sort) {
 // ---------------------------------------------------------------- launchers (geom.hip)
 void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *views, int W, int H, VertRec *vert,
                       int4 *vscr, hipStream_t s);
-// fscr: per (view, face) the four screen vertices (4 int4), written by the
-// binning count pass and read by the scatter, count and fill passes.
+// fscr: per (view, face in binning order) the four screen vertices (4 int4),
+// written by the binning count pass and read by the scatter, count and fill
+// passes; the w of corner 0 holds the canonical face id (-1: culled corner),
+// the other w's the transform's culling flags.
 // tile_cnt: 2 NT counters (NT = tiles of all views): [0, NT) the entries of
 // the faces' first four tiles, whose slots the count pass stores in bslot
 // (4 u32 per (view, face)); [NT, 2 NT) the other entries, then the tile
 // totals (the scan's input).  The scatter places the first kind from bslot
 // and the others after them with atomics on tile_fill.
-void launch_tri_bin_count(const int4 *face_c, int64_t F, int nv, const int4 *vscr, int64_t V, const Tiling &tl,
-                          uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot, hipStream_t s);
+// face_c / face_ord: the faces' corner ids and canonical ids in binning order.
+// Bin entries and fscr are indexed by binning position (entry = 2 position +
+// triangle); the fill writes records with canonical triangle ids.
+void launch_tri_bin_count(const int4 *face_c, const uint32_t *face_ord, int64_t F, int nv, const int4 *vscr,
+                          int64_t V, const Tiling &tl, uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot,
+                          hipStream_t s);
 void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
                             const uint32_t *tile_lo, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             const uint32_t *bslot, hipStream_t s);
