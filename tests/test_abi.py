@@ -64,3 +64,23 @@ def test_struct_layouts_match_header():
     assert ct.sizeof(hx.CCamera) == 16 * 4 + 8
     assert ct.sizeof(hx.CHotspot) == 16
     assert ct.sizeof(hx.CStyle) == 4 * (8 + 1 + 3 + 3 + 2 + 3 + 2 + 2)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hexfc.h compiles as strict C99 (the ABI carries no C++ or torch
+    types), and the struct sizes a C compiler gives match the binding's."""
+    import shutil
+    import subprocess
+    import paper_2009_06574_amd as hx
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "t.c"
+    src.write_text('#include <stdio.h>\n#include "hexfc.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu\\n", sizeof(hexfc_camera), sizeof(hexfc_hotspot), '
+                   'sizeof(hexfc_style), sizeof(hexfc_lod_info)); return 0; }\n')
+    exe = tmp_path / "t"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert sizes == [ct.sizeof(hx.CCamera), ct.sizeof(hx.CHotspot), ct.sizeof(hx.CStyle), ct.sizeof(hx.CLodInfo)]
