@@ -355,11 +355,13 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 // TW*TH lanes (lane = pixel), each group taking one contiguous, equal chunk of
 // the tile's bin, so that the densest tiles are not walked by one wave alone.
 // A group consumes its chunk in batches of TW*TH triangles: each lane sets up
-// one triangle into LDS, then every lane tests its pixel against the batch.
-// The count pass also stores, per bin entry and wave, the 64-bit mask of
-// covered pixels, and per group and pixel the fragments of the groups before
-// it; the fill pass reads the masks instead of testing coverage again and
-// places each group's records after those of the groups before it.
+// one triangle into LDS, then the batch's candidate (triangle, pixel) pairs
+// -- the tile pixels inside each triangle's bounding box -- are tested one
+// per lane.  The count pass also stores, per bin entry and wave, the 64-bit
+// mask of covered pixels, and per group and pixel the fragments of the
+// groups before it; the fill pass expands the masks instead of testing
+// coverage again and places each group's records after those of the groups
+// before it.
 
 template <int TW, int TH>
 struct RasterShape {
