@@ -259,7 +259,9 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
  *                         rescaled so that the opacity is the exact
  *                         1 - prod(1 - alpha).  k is ignored.
  *   rgba_out              device float [H][W][4] (as hexfc_resolve)
- * Errors: ESTATE, EINVAL (method), ERANGE (k), EOVERFLOW. */
+ * MLAB keeps a context-owned scratch of 20 bytes per fragment (the shaded
+ * fragments in primitive order), grown on first use.
+ * Errors: ESTATE, EINVAL (method), ERANGE (k), EOVERFLOW, ENOMEM. */
 enum { HEXFC_APPROX_MLAB = 1, HEXFC_APPROX_MOMENTS = 2 };
 hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
                                   int method, int k, float *rgba_out, void *stream);

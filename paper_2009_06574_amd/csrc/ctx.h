@@ -70,6 +70,7 @@ struct hexfc_ctx {
     size_t ws_bytes = 0;
     // per-frame scratch, sized for `nv_cap` views
     hexfc::DevBuf bdepth;  // per pixel: depth key of the nearest boundary-surface fragment
+    hexfc::DevBuf mlab_c, mlab_z;  // per fragment: shaded colour and depth for multi-layer alpha blending
     hexfc::DevBuf vert_b, vscr, fscr, bslot, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
         stats;
     hexfc::DevBuf count_rm_tmp;

@@ -358,9 +358,15 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
     shade_params(ctx->h_views[0].sp, hot, style);
     TRY(upload_views(ctx, 1, s));
     ResolveArgs a = resolve_args(ctx, rgba_out);
+    if (method == HEXFC_APPROX_MLAB) {  // scratch for the shaded fragments, laid out like the records
+        const uint64_t nf = std::min<uint64_t>(ctx->last_stats[ST_FRAGS], ctx->ws_bytes / 8);
+        TRY(grow(ctx, ctx->mlab_c, sizeof(float4) * std::max<uint64_t>(nf, 1)));
+        TRY(grow(ctx, ctx->mlab_z, sizeof(uint32_t) * std::max<uint64_t>(nf, 1)));
+    }
     for (int c = 0; c < NCLASS - 1; ++c)
         launch_resolve_approx(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap,
-                              (uint32_t)ctx->last_stats[ST_CLASS + c], method, k, a, s);
+                              (uint32_t)ctx->last_stats[ST_CLASS + c], method, k, a, ctx->mlab_c.as<float4>(),
+                              ctx->mlab_z.as<uint32_t>(), s);
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }

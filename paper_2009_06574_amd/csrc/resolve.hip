@@ -699,13 +699,17 @@ __device__ __forceinline__ uint32_t load_list(const ResolveArgs &a, uint32_t p, 
 
 // Multi-layer alpha blending: one wave per workgroup; the shaded fragments
 // are staged in LDS in primitive order and the wave walks them in lockstep.
+// Multi-layer alpha blending in two passes.  Shade: one wave per pixel sorts
+// the list by triangle id and shades every fragment, writing (colour,
+// opacity) and the depth field to a scratch array laid out like the records.
+// Blend: one lane per pixel runs the node insertions over its fragments in
+// that order (the insertions are sequential by definition; a lane per pixel
+// keeps them off the other 63 lanes).
 template <int R>
-__global__ void __launch_bounds__(64) k_resolve_mlab(const uint32_t *__restrict__ list, uint32_t npix, int k,
-                                                     ResolveArgs a) {
-    __shared__ float4 s_c[64 * R];   // premultiplied colour, opacity
-    __shared__ uint32_t s_z[64 * R]; // depth field
-    const int lane = threadIdx.x;
-    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(256) k_mlab_shade(const uint32_t *__restrict__ list, uint32_t npix, ResolveArgs a,
+                                                    float4 *__restrict__ mc, uint32_t *__restrict__ mz) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (wave >= npix) return;
     const uint32_t p = list[wave];
     uint64_t v[R];
@@ -716,23 +720,34 @@ __global__ void __launch_bounds__(64) k_resolve_mlab(const uint32_t *__restrict_
     const PixelRef pr = pixel_ref(a.tl, p);
     const ShadeParams &sp = a.views[pr.view].sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t e = lane * R + r;
         if (e < n) {
             const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(v[r] >> 32), pr.x, pr.y);
-            s_c[e] = make_float4(fr.r, fr.g, fr.b, fr.a);
-            s_z[e] = (uint32_t)(v[r] & 0xffffffffu);
+            mc[first + e] = make_float4(fr.r, fr.g, fr.b, fr.a);
+            mz[first + e] = (uint32_t)(v[r] & 0xffffffffu);
         }
     }
-    __syncthreads();
-    // up to k + 1 <= 9 nodes, identical on every lane
+}
+
+__global__ void __launch_bounds__(256) k_mlab_blend(const uint32_t *__restrict__ list, uint32_t npix, uint32_t nmax,
+                                                    int k, ResolveArgs a, const float4 *__restrict__ mc,
+                                                    const uint32_t *__restrict__ mz) {
+    const uint32_t i = (uint32_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix) return;
+    const uint32_t p = list[i];
+    uint32_t n = min(a.count[p], nmax);
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    if (first + n > a.rec_cap) n = 0;  // (as the shade pass: nothing was stored)
+    // up to k + 1 <= 9 nodes
     float nc0[9], nc1[9], nc2[9], nT[9];
     uint32_t nz[9];
     int cnt = 0;
     for (uint32_t e = 0; e < n; ++e) {
-        const float4 x = s_c[e];
-        const uint32_t xz = s_z[e];
+        const float4 x = mc[first + e];
+        const uint32_t xz = mz[first + e];
         int pos = 0;  // after the nodes of equal or smaller depth
 #pragma unroll
         for (int q = 0; q < 8; ++q) pos += (q < cnt && nz[q] <= xz) ? 1 : 0;
@@ -776,9 +791,10 @@ __global__ void __launch_bounds__(64) k_resolve_mlab(const uint32_t *__restrict_
             C2 += T * nc2[q];
             T *= nT[q];
         }
-    if (lane == 0)
-        reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
-            make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], 1.f - T);
+    const PixelRef pr = pixel_ref(a.tl, p);
+    const ShadeParams &sp = a.views[pr.view].sp;
+    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+        make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], 1.f - T);
 }
 
 // Moment-based transparency: wave per pixel, no sort.
@@ -856,11 +872,15 @@ __global__ void __launch_bounds__(256) k_resolve_moments(const uint32_t *__restr
 }
 
 void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, const ResolveArgs &a,
-                           hipStream_t s) {
+                           float4 *mc, uint32_t *mz, hipStream_t s) {
     if (npix == 0) return;
-#define APPROX(RV)                                                                                    \
-    if (method == 1) k_resolve_mlab<RV><<<dim3(npix), 64, 0, s>>>(pix_list, npix, k, a);              \
-    else k_resolve_moments<RV><<<dim3((npix + 3) / 4), 256, 0, s>>>(pix_list, npix, a);
+#define APPROX(RV)                                                                                              \
+    if (method == 1) {                                                                                          \
+        k_mlab_shade<RV><<<dim3((npix + 3) / 4), 256, 0, s>>>(pix_list, npix, a, mc, mz);                      \
+        k_mlab_blend<<<dim3((npix + 255) / 256), 256, 0, s>>>(pix_list, npix, 64u * (RV), k, a, mc, mz);     \
+    } else {                                                                                                    \
+        k_resolve_moments<RV><<<dim3((npix + 3) / 4), 256, 0, s>>>(pix_list, npix, a);                          \
+    }
     switch (cls) {
         case 0:
         case 1: APPROX(1); break;
