@@ -365,7 +365,7 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
     }
     for (int c = 0; c < NCLASS - 1; ++c)
         launch_resolve_approx(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap,
-                              (uint32_t)ctx->last_stats[ST_CLASS + c], method, k, a, ctx->mlab_c.as<float4>(),
+                              (uint32_t)ctx->last_stats[ST_CLASS + c], method, k, ctx->t_sort, a, ctx->mlab_c.as<float4>(),
                               ctx->mlab_z.as<uint32_t>(), s);
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;

@@ -228,8 +228,8 @@ void launch_silhouette(const Tiling &tl, int nv, const ViewParams *views, const 
 // method 2 moment-based transparency (four power moments).
 // mc, mz: multi-layer alpha blending scratch (colour and opacity, depth
 // field per fragment, laid out like the records); unused by moments.
-void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, const ResolveArgs &a,
-                           float4 *mc, uint32_t *mz, hipStream_t s);
+void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, int t_sort,
+                           const ResolveArgs &a, float4 *mc, uint32_t *mz, hipStream_t s);
 
 // Learned tail network (learned.hip).  Parameters: FP32 vector of MLP_PARAMS
 // floats: mu[9], inv_sigma[9], W1[9][64], b1[64], W2[64][64], b2[64],

@@ -732,6 +732,63 @@ __global__ void __launch_bounds__(256) k_mlab_shade(const uint32_t *__restrict__
     }
 }
 
+// The k blending nodes of one pixel (up to k + 1 <= 9 while inserting).
+struct MlabNodes {
+    float c0[9], c1[9], c2[9], T[9];
+    uint32_t z[9];
+    int cnt = 0;
+    // insert at its depth (after the nodes of equal or smaller depth); merge
+    // the last two nodes when there are k + 1
+    __device__ __forceinline__ void insert(const float4 x, uint32_t xz, int k) {
+        int pos = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pos += (q < cnt && z[q] <= xz) ? 1 : 0;
+#pragma unroll
+        for (int q = 8; q > 0; --q)
+            if (q > pos && q <= cnt) {
+                c0[q] = c0[q - 1];
+                c1[q] = c1[q - 1];
+                c2[q] = c2[q - 1];
+                T[q] = T[q - 1];
+                z[q] = z[q - 1];
+            }
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            if (q == pos) {
+                c0[q] = x.x;
+                c1[q] = x.y;
+                c2[q] = x.z;
+                T[q] = 1.f - x.w;
+                z[q] = xz;
+            }
+        ++cnt;
+        if (cnt > k) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q == cnt - 2) {
+                    c0[q] += T[q] * c0[q + 1];
+                    c1[q] += T[q] * c1[q + 1];
+                    c2[q] += T[q] * c2[q + 1];
+                    T[q] *= T[q + 1];
+                }
+            --cnt;
+        }
+    }
+    // blend the nodes front to back over the background
+    __device__ __forceinline__ float4 finish(const ShadeParams &sp) const {
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < cnt) {
+                C0 += Tr * c0[q];
+                C1 += Tr * c1[q];
+                C2 += Tr * c2[q];
+                Tr *= T[q];
+            }
+        return make_float4(C0 + Tr * sp.bg[0], C1 + Tr * sp.bg[1], C2 + Tr * sp.bg[2], 1.f - Tr);
+    }
+};
+
 __global__ void __launch_bounds__(256) k_mlab_blend(const uint32_t *__restrict__ list, uint32_t npix, uint32_t nmax,
                                                     int k, ResolveArgs a, const float4 *__restrict__ mc,
                                                     const uint32_t *__restrict__ mz) {
@@ -741,60 +798,46 @@ __global__ void __launch_bounds__(256) k_mlab_blend(const uint32_t *__restrict__
     uint32_t n = min(a.count[p], nmax);
     const uint64_t first = a.off[p] - a.off[a.pass_p0];
     if (first + n > a.rec_cap) n = 0;  // (as the shade pass: nothing was stored)
-    // up to k + 1 <= 9 nodes
-    float nc0[9], nc1[9], nc2[9], nT[9];
-    uint32_t nz[9];
-    int cnt = 0;
-    for (uint32_t e = 0; e < n; ++e) {
-        const float4 x = mc[first + e];
-        const uint32_t xz = mz[first + e];
-        int pos = 0;  // after the nodes of equal or smaller depth
-#pragma unroll
-        for (int q = 0; q < 8; ++q) pos += (q < cnt && nz[q] <= xz) ? 1 : 0;
-#pragma unroll
-        for (int q = 8; q > 0; --q)
-            if (q > pos && q <= cnt) {
-                nc0[q] = nc0[q - 1];
-                nc1[q] = nc1[q - 1];
-                nc2[q] = nc2[q - 1];
-                nT[q] = nT[q - 1];
-                nz[q] = nz[q - 1];
-            }
-#pragma unroll
-        for (int q = 0; q < 9; ++q)
-            if (q == pos) {
-                nc0[q] = x.x;
-                nc1[q] = x.y;
-                nc2[q] = x.z;
-                nT[q] = 1.f - x.w;
-                nz[q] = xz;
-            }
-        ++cnt;
-        if (cnt > k) {  // merge the last two nodes
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (q == cnt - 2) {
-                    nc0[q] += nT[q] * nc0[q + 1];
-                    nc1[q] += nT[q] * nc1[q + 1];
-                    nc2[q] += nT[q] * nc2[q + 1];
-                    nT[q] *= nT[q + 1];
-                }
-            --cnt;
+    MlabNodes nd;
+    for (uint32_t e = 0; e < n; ++e) nd.insert(mc[first + e], mz[first + e], k);
+    const PixelRef pr = pixel_ref(a.tl, p);
+    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+        nd.finish(a.views[pr.view].sp);
+}
+
+// Short lists (at most TS fragments): one lane per pixel sorts its list by
+// triangle id in LDS, then shades and inserts the fragments in that order.
+template <int TS>
+__global__ void __launch_bounds__(64) k_mlab_short(const uint32_t *__restrict__ list, uint32_t npix, int k,
+                                                   ResolveArgs a) {
+    __shared__ uint64_t col[TS][64];
+    const int lane = threadIdx.x;
+    const uint32_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 64 + lane;
+    if (idx >= npix) return;
+    const uint32_t p = list[idx];
+    uint32_t n = min(a.count[p], (uint32_t)TS);
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    if (first + n > a.rec_cap) n = 0;
+    const uint64_t *src = a.rec + first;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t r = (src[i] << 32) | (src[i] >> 32);  // triangle id first: primitive order
+        int j = (int)i;
+        while (j > 0 && col[j - 1][lane] > r) {
+            col[j][lane] = col[j - 1][lane];
+            --j;
         }
+        col[j][lane] = r;
     }
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        if (q < cnt) {
-            C0 += T * nc0[q];
-            C1 += T * nc1[q];
-            C2 += T * nc2[q];
-            T *= nT[q];
-        }
     const PixelRef pr = pixel_ref(a.tl, p);
     const ShadeParams &sp = a.views[pr.view].sp;
-    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
-        make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], 1.f - T);
+    const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    MlabNodes nd;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t r = col[i][lane];
+        const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(r >> 32), pr.x, pr.y);
+        nd.insert(make_float4(fr.r, fr.g, fr.b, fr.a), (uint32_t)(r & 0xffffffffu), k);
+    }
+    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = nd.finish(sp);
 }
 
 // Moment-based transparency: wave per pixel, no sort.
@@ -871,8 +914,8 @@ __global__ void __launch_bounds__(256) k_resolve_moments(const uint32_t *__restr
     }
 }
 
-void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, const ResolveArgs &a,
-                           float4 *mc, uint32_t *mz, hipStream_t s) {
+void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, int t_sort,
+                           const ResolveArgs &a, float4 *mc, uint32_t *mz, hipStream_t s) {
     if (npix == 0) return;
 #define APPROX(RV)                                                                                              \
     if (method == 1) {                                                                                          \
@@ -880,6 +923,13 @@ void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int
         k_mlab_blend<<<dim3((npix + 255) / 256), 256, 0, s>>>(pix_list, npix, 64u * (RV), k, a, mc, mz);     \
     } else {                                                                                                    \
         k_resolve_moments<RV><<<dim3((npix + 3) / 4), 256, 0, s>>>(pix_list, npix, a);                          \
+    }
+    if (cls == 0 && method == 1) {  // short lists: a lane per pixel
+        const dim3 g((npix + 63) / 64);
+        if (t_sort <= 16) k_mlab_short<16><<<g, 64, 0, s>>>(pix_list, npix, k, a);
+        else if (t_sort <= 32) k_mlab_short<32><<<g, 64, 0, s>>>(pix_list, npix, k, a);
+        else k_mlab_short<64><<<g, 64, 0, s>>>(pix_list, npix, k, a);
+        return;
     }
     switch (cls) {
         case 0:
