@@ -914,6 +914,68 @@ __global__ void __launch_bounds__(256) k_resolve_moments(const uint32_t *__restr
     }
 }
 
+// Short lists (at most TS fragments; mostly empty pixels): one lane per
+// pixel, the fragments shaded twice (moments, then the bound per fragment)
+// instead of being held.
+template <int TS>
+__global__ void __launch_bounds__(256) k_moments_short(const uint32_t *__restrict__ list, uint32_t npix,
+                                                       ResolveArgs a) {
+    const uint32_t idx = xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (idx >= npix) return;
+    const uint32_t p = list[idx];
+    uint32_t n = min(a.count[p], (uint32_t)TS);
+    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    if (first + n > a.rec_cap) n = 0;
+    const uint64_t *src = a.rec + first;
+    const PixelRef pr = pixel_ref(a.tl, p);
+    const ViewParams &vp = a.views[pr.view];
+    const ShadeParams &sp = vp.sp;
+    const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+    const double zs = 1.0 / ((double)vp.w1 - (double)vp.w0);
+    auto warp = [&](uint64_t r) {
+        const double w = 1048576.0 / (double)(KMAX - (uint32_t)(r >> 32));
+        return 2.0 * fmin(fmax((w - (double)vp.w0) * zs, 0.0), 1.0) - 1.0;
+    };
+    double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t r = src[i];
+        const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(r & 0xffffffffu), pr.x, pr.y);
+        const double ab = -log1p(-fmin((double)fr.a, 1.0 - 1e-6)), xw = warp(r);
+        double xp = 1.0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            b[j] += ab * xp;
+            xp *= xw;
+        }
+    }
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    if (b[0] > 0.0) {
+        const double ref[5] = {1.0, 0.0, 0.375, 0.0, 0.375};
+        double m[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) m[j] = (1.0 - MOM_BETA) * (b[j] / b[0]) + MOM_BETA * ref[j];
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, W = 0.0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint64_t r = src[i];
+            const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(r & 0xffffffffu), pr.x, pr.y);
+            const double T = exp(-b[0] * moment_fraction(m, warp(r)));
+            c0 += T * fr.r;
+            c1 += T * fr.g;
+            c2 += T * fr.b;
+            W += T * fr.a;
+        }
+        const double At = -expm1(-b[0]);
+        const double sc = W > 0.0 ? At / W : 0.0;
+        C0 = (float)(c0 * sc);
+        C1 = (float)(c1 * sc);
+        C2 = (float)(c2 * sc);
+        A = (float)At;
+    }
+    const float T = 1.f - A;
+    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+        make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
+}
+
 void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int method, int k, int t_sort,
                            const ResolveArgs &a, float4 *mc, uint32_t *mz, hipStream_t s) {
     if (npix == 0) return;
@@ -929,6 +991,13 @@ void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int
         if (t_sort <= 16) k_mlab_short<16><<<g, 64, 0, s>>>(pix_list, npix, k, a);
         else if (t_sort <= 32) k_mlab_short<32><<<g, 64, 0, s>>>(pix_list, npix, k, a);
         else k_mlab_short<64><<<g, 64, 0, s>>>(pix_list, npix, k, a);
+        return;
+    }
+    if (cls == 0) {
+        const dim3 g((npix + 255) / 256);
+        if (t_sort <= 16) k_moments_short<16><<<g, 256, 0, s>>>(pix_list, npix, a);
+        else if (t_sort <= 32) k_moments_short<32><<<g, 256, 0, s>>>(pix_list, npix, a);
+        else k_moments_short<64><<<g, 256, 0, s>>>(pix_list, npix, a);
         return;
     }
     switch (cls) {
