@@ -26,8 +26,11 @@
  *   - importance = normalised (1 - scaled Jacobian) unless a scalar is given.
  *
  * Pins: see tests/test_oracle_*.py (closed forms, brute force, invariants).
- * The halo width/alpha and darkening constants are "parity unpinned" except
- * through their reduction to Eq. 1 when set to zero.
+ * The edge colour (TF of the nearest visible edge's importance, darkened in
+ * focus), the halo band and its white colour, and the accent brightening are
+ * pinned on a two-cell orthographic setup whose distances and importances are
+ * known by construction (tests/test_oracle_edges.py); their default values
+ * (halo width, darkening, brightening) are parameters the paper leaves open.
  */
 #include <stdint.h>
 #include <stdlib.h>
