@@ -370,15 +370,19 @@ struct RasterShape {
 };
 
 // Synchronise the lanes of one group (the NT lanes that work on one bin
-// chunk).  A one-wave group only needs its own LDS traffic drained and no
-// code motion across the point: the LDS executes a wave's accesses in order.
-// Wider groups need the workgroup barrier, and then every group of the
-// workgroup must reach the same number of them.
+// chunk).  A one-wave group needs its LDS stores ordered before the loads
+// that follow and no code motion of LDS accesses across the point: a
+// wavefront-scope release/acquire pair around the wave barrier gives both
+// (the compiler may not move memory operations across the fences, and the
+// release waits for the wave's outstanding LDS stores).  Wider groups need
+// the workgroup barrier, and then every group of the workgroup must reach the
+// same number of them.
 template <int NW>
 __device__ __forceinline__ void group_sync() {
     if constexpr (NW == 1) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
         __syncthreads();
     }

@@ -157,10 +157,18 @@ def test_mlp_backward(n):
     log(f"[mlp] backward n={n} rel vs bf16 model {rel_b:.2e} vs fp64 {rel_64:.2e}")
     assert rel_b <= 2e-3
     assert rel_64 <= 1e-2
-    # every parameter block, separately
+    # every parameter block, separately, and element by element against the
+    # block's largest gradient (the model reproduces the kernels' BF16 rounding
+    # points; the FP32 sums over rows run in another order, which can move an
+    # intermediate across a BF16 rounding boundary now and then)
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
         s = slice(*mlp.OFF[k])
         assert np.linalg.norm(g[s] - g64[s]) <= 2e-2 * np.linalg.norm(g64[s]) + 1e-9, k
+        eb = np.abs(g[s] - gb[s]).max() / np.abs(gb[s]).max()
+        e64 = np.abs(g[s] - g64[s]).max() / np.abs(g64[s]).max()
+        log(f"[mlp] backward n={n} {k}: max element error / block max: vs bf16 model {eb:.2e}, vs fp64 {e64:.2e}")
+        assert eb <= 5e-3, (k, eb)
+        assert e64 <= 3e-2, (k, e64)
 
 
 def test_mlp_backward_accumulates():

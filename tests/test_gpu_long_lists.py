@@ -1,0 +1,100 @@
+"""GPU parity on deterministic long per-pixel lists.
+
+A column of n cells stacked along the view axis and seen head-on gives every
+central pixel n + 1 fragments (one per layer face), so each length class of
+the resolve is reached on purpose, not by chance: 70, 200, 300, 600, 1100,
+2000 and 3000 fragments per pixel.  Layers get random importances (random
+per-cell scalars), so colours differ from layer to layer and a wrong order
+changes the blend.  Stacks whose layers coincide in depth give equal depth
+keys, which the order breaks by triangle (face) id: every layer at one depth,
+and layers coinciding in pairs.  Counts, the sorted records and the RGBA
+image are compared with the FP64 oracle element by element (RGBA within
+1e-4 per channel; the faces are nearly transparent, so the blend runs
+through the whole list).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from tests._parity import gpu_lists, gpu_renderer, log, rgba_mismatch
+
+pytestmark = pytest.mark.gpu
+
+W = 24
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_lib):
+    return oracle_lib
+
+
+def stack(n_layers, depth=3.0, pairs=False, flat=False, seed=0):
+    """n_layers - 1 cells of a 1 x 1 column along z in [-depth, 0] (every layer
+    at z = -1 when flat; layers coinciding in pairs when pairs), random cell
+    scalars; a 24 x 24 view along -z from z = 1.2."""
+    n = n_layers - 1
+    m = synth.box_grid(1, 1, n, size=(1.0, 1.0, depth), origin=(-0.5, -0.5, -depth))
+    xyz = m.xyz.astype(np.float64)
+    k = np.rint((xyz[:, 2] + depth) / depth * n).astype(np.int64)  # layer index of each vertex
+    if flat:
+        xyz[:, 2] = -1.0
+    elif pairs:
+        xyz[:, 2] = -depth + (k // 2) * (2 * depth / n)
+    m.xyz = xyz.astype(np.float32)
+    m.cell_scalar = np.random.default_rng(seed).uniform(0, 1, m.C).astype(np.float32)
+    m.name = f"stack{n_layers}{'flat' if flat else ''}{'pairs' if pairs else ''}"
+    cam = synth.make_camera((0.0, 0.0, 1.2), (0.0, 0.0, -1.0), W, W, fovy_deg=30.0)
+    return m, cam
+
+
+def see_through_style(cam, a=0.002):
+    return synth.default_style(cam, tf_a_lo=a, tf_a_hi=4 * a, k_focus=2.0, lod=0)
+
+
+def compare(orc, m, cam, hot, st, ws=1 << 28):
+    log(f"[long] {m.name}: {m.C} cells")
+    ref = orc.render(m, cam, hot, st)
+    r = gpu_renderer(m, ws)
+    c, o, rec = gpu_lists(r, cam)
+    assert np.array_equal(c, ref["count"]), np.nonzero(c != ref["count"])[0][:10]
+    assert np.array_equal(o, ref["off"])
+    bad_rec = np.nonzero(rec != ref["rec"])[0]
+    assert bad_rec.size == 0, (bad_rec[:5], rec[bad_rec[:5]], ref["rec"][bad_rec[:5]])
+    img = r.render(cam, hot, st).cpu().numpy().reshape(-1, 4)
+    d = np.abs(img - ref["rgba"]).max()
+    bad, excl = rgba_mismatch(img, ref["rgba"], ref["ncand"], ref["cand_off"], ref["cand"])
+    log(f"[long] {m.name}: max list {c.max()}, {int(c.sum())} fragments, stats {r.frame_stats()['classes']}, "
+        f"max |d rgba| {d:.2e}")
+    assert bad.size == 0, (bad[:10], img[bad[:3]], ref["rgba"][bad[:3]])
+    assert excl.size == 0
+    return r, ref, c, img
+
+
+@pytest.mark.parametrize("n_layers", [70, 200, 300, 600, 1100, 2000])
+def test_stack_every_length_class(orc, n_layers):
+    m, cam = stack(n_layers)
+    st = see_through_style(cam, a=min(0.002, 2.0 / n_layers))
+    hot = synth.Hotspot((0.1, 0.05, -1.0), 0.8)
+    r, ref, c, img = compare(orc, m, cam, hot, st)
+    assert int(c.max()) >= n_layers
+    # the blend really reached the back: the central pixel (far from every
+    # layer's edges) is not opaque
+    centre = (W // 2) * W + W // 2
+    assert c[centre] == n_layers and img[centre, 3] < 0.999
+
+
+@pytest.mark.parametrize("n_layers,kw", [(40, dict(flat=True)), (300, dict(flat=True)), (700, dict(flat=True)),
+                                         (260, dict(pairs=True)), (1500, dict(pairs=True))])
+def test_stack_equal_depths(orc, n_layers, kw):
+    """Equal depth keys: the order is the triangle (face) id order."""
+    m, cam = stack(n_layers, **kw)
+    st = see_through_style(cam, a=min(0.002, 2.0 / n_layers))
+    hot = synth.Hotspot((0.1, 0.05, -1.0), 0.8)
+    r, ref, c, img = compare(orc, m, cam, hot, st)
+    # ties really occur
+    cnt, off, rec = ref["count"], ref["off"], ref["rec"]
+    p = int(np.argmax(cnt))
+    depths = (rec[off[p]:off[p + 1]] >> np.uint64(32))
+    assert np.unique(depths).size < depths.size
