@@ -219,58 +219,68 @@ def main():
     log(f"[bench] upload {time.perf_counter() - t0:.1f} s")
     out = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
     nv = len(cams)
+    # Statistics of each view (fragments, bin entries, per-class sizes): one
+    # frame per view, read back; the timed frames below read nothing back
+    # (render_frame neither waits nor copies), so fragments/s counts the
+    # known fragments of the views rendered.
+    view_stats = []
+    for k in range(nv):
+        r.render(cams[k], hots[k], styles[k], out=out)
+        view_stats.append(r.frame_stats())
     for i in range(args.warmup):
         r.render(cams[i % nv], hots[i % nv], styles[i % nv], out=out)
     torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} frames)")
-    r.set_profiling(True)
-    r.kernel_times()
-    frags = 0
-    stats = []
+    log(f"[bench] warmup done ({nv} sizing + {args.warmup} frames)")
+    seq = [(args.warmup + i) % nv for i in range(args.steps)]
+    frags = sum(view_stats[k]["fragments"] for k in seq)
+    bins = sum(view_stats[k]["bins"] for k in seq)
+    # the clean timing: no per-launch events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        k = (args.warmup + i) % nv
+    for k in seq:
         r.render(cams[k], hots[k], styles[k], out=out)
-        st = r.frame_stats()
-        frags += st["fragments"]
-        stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kt = r.kernel_times()
-    r.set_profiling(False)
+    fl, over = r.batch_status()
+    assert not over, "a timed frame outgrew its sizes"
     ms_frame = 1000.0 * dt / args.steps
     log(f"[bench] {args.steps} frames in {dt:.3f} s: {ms_frame:.3f} ms/frame, {frags / dt / 1e9:.3f} G fragments/s")
+    # the same frames again with HIP events around every launch (per-kernel times)
+    r.set_profiling(True)
+    r.kernel_times()
+    for k in seq:
+        r.render(cams[k], hots[k], styles[k], out=out)
+    torch.cuda.synchronize()
+    kt = r.kernel_times()
+    r.set_profiling(False)
 
-    # roofline of the dominant list kernel (fill or a resolve class), from the
-    # HIP events recorded around its launches on the render stream
+    # rooflines of the list kernels from the HIP events recorded around their
+    # launches on the render stream: the fill (8 B per fragment written, 4 B
+    # per bin entry and 8 B of offsets per pixel read), the resolve (8 B per
+    # fragment read, 32 B per pixel: count, offsets, RGBA) and the coverage
+    # count (4 B per bin entry read, 4 B per pixel written)
     P = 1920 * 1080
-    sum_cls_f = np.zeros(8)
-    sum_cls_p = np.zeros(8)
-    bins = 0
-    for st in stats:
-        sum_cls_f += np.asarray(st["class_fragments"], dtype=np.float64)
-        sum_cls_p += np.asarray(st["classes"], dtype=np.float64)
-        bins += st["bins"]
-    alg = {}
-    if "fill" in kt:
-        alg["fill"] = 8.0 * frags + 4.0 * bins + 8.0 * P * args.steps
-    for c in range(7):
-        k = f"resolve_c{c}"
-        if k in kt:
-            alg[k] = 8.0 * sum_cls_f[c] + 32.0 * sum_cls_p[c]
-    dom = max(alg, key=lambda k: kt[k][0])
-    ms_dom, n_dom = kt[dom]
-    achieved = (alg[dom] / n_dom) / (ms_dom / n_dom * 1e-3) / 1e9
-    traffic = measured_traffic(dom) if args.grid == 128 else None
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if traffic is None else int(traffic), kernel=dom,
-                    avg_launch_ms=round(ms_dom / n_dom, 4),
-                    bytes_per_launch=int(alg[dom] / n_dom))
+    alg = {"fill": 8.0 * frags + 4.0 * bins + 8.0 * P * args.steps,
+           "resolve": 8.0 * frags + 32.0 * P * args.steps,
+           "count": 4.0 * bins + 4.0 * P * args.steps}
+    rooflines = {}
+    for k, b in alg.items():
+        if k not in kt:
+            continue
+        ms_k, n_k = kt[k]
+        ach = (b / n_k) / (ms_k / n_k * 1e-3) / 1e9
+        traffic = measured_traffic(k) if args.grid == 128 else None
+        rooflines[k] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(ach / HBM_PEAK_GBS, 4), traffic=None if traffic is None else int(traffic),
+                            kernel=k, avg_launch_ms=round(ms_k / n_k, 4), bytes_per_launch=int(b / n_k))
+    dom = max(("fill", "resolve"), key=lambda k: kt[k][0])
+    roofline = dict(rooflines[dom])
+    roofline["others"] = {k: {x: v[x] for x in ("achieved", "frac", "avg_launch_ms", "bytes_per_launch", "traffic")}
+                          for k, v in rooflines.items() if k != dom}
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
-    log(f"[bench] per-frame kernel ms: {kernel_ms}")
-    log(f"[bench] dominant {dom}: {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
+    log(f"[bench] per-frame kernel ms: {kernel_ms} (sum {sum(kernel_ms.values()):.3f})")
+    for k, v in rooflines.items():
+        log(f"[bench] {k}: {v['achieved']:.1f} GB/s ({v['frac']:.1%} of HBM peak), {v['avg_launch_ms']:.4f} ms")
 
     learned = None
     if not args.no_learned:

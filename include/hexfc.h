@@ -162,14 +162,28 @@ hexfc_status hexfc_build_fragment_lists(hexfc_ctx *ctx, const hexfc_camera *cam,
 
 /* Resolve the last built lists: sort each pixel's list front to back, shade
  * every fragment (Eq. 1-4) and composite (Section 4.2) over the background.
+ * One persistent launch takes the pixels longest list first; lists of any
+ * length are sorted (those longer than 2048 fragments in place in the
+ * workspace, which leaves each list's records reordered, not changed).
  * rgba_out: device float [height][width][4], premultiplied colour plus
- * accumulated opacity.  Errors: ESTATE (no lists), EINVAL (radius <= 0),
- * EOVERFLOW (a list longer than 2048 fragments). */
+ * accumulated opacity.  Does not wait for the stream.  Errors: ESTATE (no
+ * lists), EINVAL (radius <= 0). */
 hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
                            float *rgba_out, void *stream);
 
 /* One frame: build + resolve, in several screen passes when the fragments
- * exceed the workspace.  Same outputs and errors as the two calls above. */
+ * exceed the workspace (each pass fills and resolves a range of screen tiles
+ * that the device plans from the pixels' fragment counts).  Nothing waits for
+ * the stream and nothing is copied to the host, so the call can be captured in
+ * a HIP graph, with one exception: the first frame of a mesh, viewport, tiling
+ * and workspace waits once for its statistics (bin sizes, number of screen
+ * passes), and must not be captured.  Later frames use the sizes learned so
+ * far and grow them, without waiting, from counters the device publishes to
+ * host-mapped memory after every frame; a frame that outgrows them (more bin
+ * entries, more screen passes) has an invalid output, is flagged (see
+ * hexfc_batch_status) and makes the next call grow.  Same outputs as the two
+ * calls above.  Errors: as above, EOVERFLOW (first frame: one screen tile's
+ * fragments exceed the workspace), ESTATE (the first frame inside a capture). */
 hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const hexfc_hotspot *hot,
                                 const hexfc_style *style, float *rgba_out, void *stream);
 
@@ -188,7 +202,9 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
                                 const hexfc_style *styles, float *rgba_out, void *stream);
 
 /* Waits for `stream`, then reports the fragments of the last batch (or frame)
- * and whether it overflowed the captured sizes (its output is then invalid). */
+ * and whether it overflowed the sizes it was enqueued with (more triangle-bin
+ * entries, more screen passes, or more fragments than one pass holds): its
+ * output is then invalid. */
 hexfc_status hexfc_batch_status(hexfc_ctx *ctx, uint64_t *fragments, int *overflow, void *stream);
 
 /* Autotuner: times every tile shape x t_sort in {0, 8, 16, 32, 64} on the
@@ -208,27 +224,29 @@ hexfc_status hexfc_autotune(hexfc_ctx *ctx, int n, const hexfc_camera *cams, con
  * on them.  Invalidates built lists. */
 hexfc_status hexfc_set_tuning(hexfc_ctx *ctx, int tile_w, int tile_h, int t_sort);
 
-/* Statistics of the last build/render (host copy, no synchronisation):
- * out[0] bin entries, out[1] fragments, out[2] screen passes, out[8..15]
- * pixels per length class (0: n <= t_sort; 1..6: n <= 64, 128, 256, 512,
- * 1024, 2048; 7: longer), out[16..23] fragments per length class,
- * out[24..31] pixels per class that the last hexfc_resolve_learned sent to
- * the exact fallback (current once hexfc_batch_status has synchronised the
- * statistics).  n = number of entries wanted (<= 32). */
+/* Statistics of the last build/render; waits for the stream of the last
+ * call: out[0] bin entries, out[1] fragments, out[2] screen passes planned,
+ * out[4] flags (nonzero: the frame outgrew its sizes, see
+ * hexfc_batch_status), out[8..15] pixels per length class (0: n <= t_sort;
+ * 1..7: n <= 64, 128, 256, 512, 1024, 2048, longer), out[16..23] fragments
+ * per length class, out[24..31] pixels per class that the last
+ * hexfc_resolve_learned sent to the exact fallback.  n = number of entries
+ * wanted (<= 32). */
 hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n);
 
 /* Per-launch timing with HIP events recorded on the launch stream (off by
- * default).  hexfc_get_kernel_times waits for the recorded events, returns the
- * accumulated milliseconds and launch counts per kernel and resets them.
- * Kernel index: 0 transform, 1 triangle binning (count + tile scan),
- * 2 bin scatter, 3 coverage count, 4 pixel scan, 5 length classes, 6 pass
- * plan, 7 list fill, 8 + c resolve of length class c (c = 0..6), 16 learned
- * tail: head and features, 17 learned tail: network and compose, 18 learned
- * tail: exact fallback.  n = number of entries wanted (<= 19). */
+ * default; never inside a stream capture).  hexfc_get_kernel_times waits for
+ * the recorded events, returns the accumulated milliseconds and launch counts
+ * per kernel and resets them.  Kernel index: 0 transform, 1 triangle binning
+ * (count + tile scan), 2 bin scatter, 3 coverage count, 4 pixel scan,
+ * 5 length classes, 6 pass plan, 7 list fill, 8 resolve (every length class,
+ * one persistent launch per pass), 9 learned tail: head and features,
+ * 10 learned tail: network and compose, 11 learned tail: exact fallback.
+ * n = number of entries wanted (<= 12). */
 hexfc_status hexfc_set_profiling(hexfc_ctx *ctx, int enable);
 hexfc_status hexfc_get_kernel_times(hexfc_ctx *ctx, double *ms_out, uint64_t *launches_out, int n);
 
-/* Total fragments of the last build/render (host value). */
+/* Total fragments of the last build/render (waits for the stream of the last call). */
 hexfc_status hexfc_get_total_fragments(hexfc_ctx *ctx, uint64_t *out);
 
 /* Parity export of the last built lists, row-major pixel order:

@@ -285,15 +285,16 @@ class Renderer:
         return int(v.value)
 
     def frame_stats(self) -> dict:
+        """Statistics of the last frame (waits for it)."""
         a = (ct.c_uint64 * 32)()
         self._check(self.lib.hexfc_get_frame_stats(self.ctx, a, 32))
-        return dict(bins=int(a[0]), fragments=int(a[1]), passes=int(a[2]),
+        return dict(bins=int(a[0]), fragments=int(a[1]), passes=int(a[2]), flags=int(a[4]),
                     classes=[int(a[8 + i]) for i in range(8)],
                     class_fragments=[int(a[16 + i]) for i in range(8)],
                     fallback=[int(a[24 + i]) for i in range(8)])
 
-    KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill") + tuple(
-        f"resolve_c{c}" for c in range(8)) + ("tail_features", "mlp_apply", "fallback")
+    KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill", "resolve",
+               "tail_features", "mlp_apply", "fallback")
 
     APPROX_METHODS = {"mlab": 1, "moments": 2}
 

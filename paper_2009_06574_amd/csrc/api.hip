@@ -87,11 +87,27 @@ hexfc_status hexfc_create(int device, hexfc_ctx **out) {
     hexfc_ctx *ctx = new (std::nothrow) hexfc_ctx();
     if (!ctx) return HEXFC_ENOMEM;
     ctx->device = device;
+    void *pub = nullptr;
     if (hipSetDevice(device) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_stats, sizeof(uint64_t) * ST_COUNT, hipHostMallocDefault) != hipSuccess ||
         ctx->stats.ensure(sizeof(uint64_t) * ST_COUNT) != hipSuccess ||
+        ctx->persist.ensure(sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
+        hipMemset(ctx->persist.p, 0, sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
+        hipHostMalloc(&pub, sizeof(uint64_t) * (PS_COUNT + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->d_pub, pub, 0) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
+        ctx->h_stats = nullptr;
+        if (pub) (void)hipHostFree(pub);
+        delete ctx;
+        return HEXFC_EDEVICE;
+    }
+    memset(pub, 0, sizeof(uint64_t) * (PS_COUNT + 1));
+    ctx->h_pub = reinterpret_cast<volatile uint64_t *>(pub);
+    resolve_grids(device, ctx->res_grid);
+    if (hipDeviceSynchronize() != hipSuccess) {  // (the counters' zeroing has landed)
+        (void)hipHostFree(ctx->h_stats);
         delete ctx;
         return HEXFC_EDEVICE;
     }
@@ -352,6 +368,8 @@ hexfc_status hexfc_upload_mesh(hexfc_ctx *ctx, const float *xyz, int64_t V, cons
     ctx->V = V;
     ctx->C = C;
     ctx->F = F;
+    ctx->mesh_gen += 1;
+    ctx->sized = false;
     ctx->lists_valid = false;
     ctx->have_frame = false;
     ctx->vert_b_views = 0;

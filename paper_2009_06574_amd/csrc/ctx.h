@@ -13,24 +13,29 @@
 
 namespace hexfc {
 
-// Device allocation that only grows.
+// Device allocation that only grows.  A replaced allocation is kept until the
+// context is destroyed: work already enqueued, and HIP graphs a caller
+// captured from earlier frames, may still use it.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    std::vector<void *> retired;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() {
         if (p) (void)hipFree(p);
+        for (void *q : retired) (void)hipFree(q);
     }
     hipError_t ensure(size_t n) {
         if (n <= bytes && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        hipError_t e = hipMalloc(&p, n ? n : 256);
-        if (e == hipSuccess) bytes = n;
-        return e;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, n ? n : 256);
+        if (e != hipSuccess) return e;
+        if (p) retired.push_back(p);
+        p = q;
+        bytes = n;
+        return hipSuccess;
     }
     template <class T> T *as() const { return reinterpret_cast<T *>(p); }
 };
@@ -72,7 +77,7 @@ struct hexfc_ctx {
     hexfc::DevBuf bdepth;  // per pixel: depth key of the nearest boundary-surface fragment
     hexfc::DevBuf mlab_c, mlab_z;  // per fragment: shaded colour and depth for multi-layer alpha blending
     hexfc::DevBuf vert_b, vscr, fscr, bslot, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
-        stats;
+        stats, persist;
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists
     hexfc::DevBuf l_head, l_feat, l_pix, l_fb;
@@ -80,6 +85,18 @@ struct hexfc_ctx {
     uint64_t bin_cap = 0;
     int64_t cls_cap = 0;
     uint64_t *h_stats = nullptr;  // pinned
+    // host-mapped copy of the device's cross-frame counters (PersistSlot),
+    // written by each frame's closing kernel: [0] frames finished, [1 + i] slot i
+    volatile uint64_t *h_pub = nullptr;
+    uint64_t *d_pub = nullptr;  // its device address
+    int res_grid[3] = {1, 1, 1};  // persistent resolve grids (t_sort <= 16, 32, 64)
+    // single frames: sizes learned for the current mesh, viewport, tiling and
+    // workspace (the first frame of such a combination waits once to learn them)
+    bool sized = false;
+    int64_t frame_sig[7] = {0, 0, 0, 0, 0, 0, 0};
+    int passes_launch = 1;  // screen passes enqueued per frame
+    uint64_t mesh_gen = 0;  // bumped by every upload
+    hipStream_t last_stream = nullptr;
     hipStream_t cap_stream = nullptr;  // non-blocking stream used to capture the batch graph
     hexfc::BatchGraph bg;
     // state of the last build
@@ -87,6 +104,7 @@ struct hexfc_ctx {
     int nv = 1;
     bool lists_valid = false;
     bool have_frame = false;
+    bool stats_known = false;  // last_stats holds the class sizes of the current lists
     uint64_t last_frags = 0;
     uint64_t last_stats[hexfc::ST_COUNT] = {};
     std::vector<hexfc::ViewParams> h_views;
@@ -108,6 +126,7 @@ struct hexfc_ctx {
         }
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (h_pub) (void)hipHostFree((void *)h_pub);
     }
 };
 

@@ -152,8 +152,27 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
     return HEXFC_OK;
 }
 
-// Transform, bin, count, scan, classify (and plan screen passes for one view).
-void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool plan) {
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+uint64_t *pass_tiles(hexfc_ctx *ctx, int k) { return ctx->stats.as<uint64_t>() + ST_PASS + k; }
+
+// The front half of a frame of nv views: transform, binning, coverage count,
+// pixel scan; then either the plan of screen passes under the workspace
+// budget (single frames, FRONT_PLAN) or one pass over every tile with its
+// pixels classified at once (frames that must fit the workspace: the list
+// build and batches, FRONT_SINGLE).
+enum FrontMode { FRONT_PLAN, FRONT_SINGLE };
+
+void enqueue_classify(hexfc_ctx *ctx, int nv, int k, hipStream_t s) {
+    ScopedTimer tm(ctx, s, KID_CLASSIFY);
+    launch_classify(ctx->tl, nv, k, ctx->count.as<uint32_t>(), ctx->t_sort, ctx->cls.as<uint32_t>(), ctx->cls_cap,
+                    ctx->stats.as<uint64_t>(), s);
+}
+
+void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, FrontMode mode) {
     const int64_t TP = (int64_t)tl.TW * tl.TH;
     const int64_t nt = (int64_t)tl.ntiles * nv;
     const int64_t np = nt * TP;
@@ -161,6 +180,7 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
     const int4 *fc = ctx->face_c.as<int4>();
     int4 *vscr = ctx->vscr.as<int4>();
     const uint64_t budget = ctx->ws ? ctx->ws_bytes / 8 : 0;
+    ctx->tl = tl;
     launch_zero_u64(stats, ST_COUNT, s);
     launch_zero_u32(ctx->tile_cnt.as<uint32_t>(), 2 * nt, s);
     launch_zero_u32(ctx->tile_fill.as<uint32_t>(), nt, s);
@@ -193,36 +213,39 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, bool
         launch_scan_u32_u64(ctx->count.as<uint32_t>(), np, ctx->off.as<uint64_t>(), ctx->scan_tmp.as<uint64_t>(),
                             stats + ST_FRAGS, s);
     }
-    {
-        ScopedTimer tm(ctx, s, KID_CLASSIFY);
-        launch_classify(tl, 0, nt, ctx->count.as<uint32_t>(), ctx->t_sort, ctx->cls.as<uint32_t>(), ctx->cls_cap,
-                        stats, s);
-    }
-    if (plan) {
+    if (mode == FRONT_PLAN) {
         ScopedTimer tm(ctx, s, KID_PLAN);
         launch_plan(tl, ctx->off.as<uint64_t>(), budget, stats, s);
+    } else {
+        launch_single_pass(nt, stats, s);
+        enqueue_classify(ctx, nv, 0, s);
     }
 }
 
+// Waits for `s` and copies the device statistics of the last frame to the host.
 hexfc_status read_stats(hexfc_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_stats, ctx->stats.p, sizeof(uint64_t) * ST_COUNT, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     memcpy(ctx->last_stats, ctx->h_stats, sizeof(ctx->last_stats));
+    ctx->stats_known = true;
     return HEXFC_OK;
 }
 
-hexfc_status upload_views(hexfc_ctx *ctx, int nv, hipStream_t s) {
+// View parameters to the device: a single view by value through a kernel
+// argument (a graph that captures the frame keeps them), a batch by copy.
+hexfc_status set_views(hexfc_ctx *ctx, int nv, hipStream_t s) {
+    if (nv == 1) {
+        launch_set_view(ctx->h_views[0], ctx->views.as<ViewParams>(), s);
+        return HEXFC_OK;
+    }
     // (pageable source: the runtime stages it before returning, so the host
     // copy may change right after)
     HIPCHK(ctx, hipMemcpyAsync(ctx->views.p, ctx->h_views.data(), sizeof(ViewParams) * nv, hipMemcpyHostToDevice, s));
     return HEXFC_OK;
 }
 
-// Everything up to the fill for nv views with the given cameras (one sync;
-// a second pass only when the triangle bins had to grow).
-hexfc_status prepare(hexfc_ctx *ctx, int nv, const hexfc_camera *cams, hipStream_t s, bool plan) {
+hexfc_status check_views(hexfc_ctx *ctx, int nv, const hexfc_camera *cams) {
     if (ctx->V == 0) FAIL(ctx, HEXFC_ESTATE, "no mesh uploaded");
-    TRY(set_device(ctx));
     if ((int)ctx->h_views.size() < nv) ctx->h_views.resize(nv);
     for (int v = 0; v < nv; ++v) {
         TRY(check_camera(ctx, &cams[v], ctx->h_views[v].M));
@@ -230,11 +253,20 @@ hexfc_status prepare(hexfc_ctx *ctx, int nv, const hexfc_camera *cams, hipStream
             FAIL(ctx, HEXFC_EINVAL, "all views of a batch must have the same viewport");
         depth_range(ctx, &cams[v], ctx->h_views[v]);
     }
+    return HEXFC_OK;
+}
+
+// The front half of a frame with one wait: sizes the per-frame buffers,
+// enqueues the front and reads the statistics back (a second time when the
+// triangle bins had to grow).
+hexfc_status prepare(hexfc_ctx *ctx, int nv, const hexfc_camera *cams, hipStream_t s, FrontMode mode) {
+    TRY(set_device(ctx));
+    TRY(check_views(ctx, nv, cams));
     const Tiling tl = make_tiling(ctx, cams[0].width, cams[0].height);
     TRY(ensure_frame_buffers(ctx, nv, tl));
-    TRY(upload_views(ctx, nv, s));
+    TRY(set_views(ctx, nv, s));
     for (int attempt = 0; attempt < 2; ++attempt) {
-        enqueue_front(ctx, nv, tl, s, plan);
+        enqueue_front(ctx, nv, tl, s, mode);
         TRY(read_stats(ctx, s));
         const uint64_t need = ctx->last_stats[ST_BINS];
         if (need <= ctx->bin_cap) break;
@@ -243,14 +275,13 @@ hexfc_status prepare(hexfc_ctx *ctx, int nv, const hexfc_camera *cams, hipStream
         TRY(grow(ctx, ctx->masks, sizeof(uint64_t) * cap * (tl.TW * tl.TH / 64)));
         ctx->bin_cap = cap;
     }
-    ctx->tl = tl;
     ctx->nv = nv;
     ctx->have_frame = true;
     ctx->last_frags = ctx->last_stats[ST_FRAGS];
     return HEXFC_OK;
 }
 
-ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba) {
+ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba, int pass) {
     ResolveArgs a;
     a.tl = ctx->tl;
     a.mesh.posq = ctx->posq.as<int4>();
@@ -266,39 +297,83 @@ ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba) {
     a.rec = ctx->ws;
     a.rec_cap = ctx->ws_bytes / 8;
     a.pass_p0 = 0;
+    a.pass_tiles = pass >= 0 ? pass_tiles(ctx, pass) : nullptr;
     a.rgba = rgba;
     a.sorted_out = nullptr;
     a.off_rm = nullptr;
     return a;
 }
 
-void launch_classes(hexfc_ctx *ctx, const ResolveArgs &a, const uint64_t *cls_counts, const uint64_t *cls_dev,
-                    hipStream_t s) {
-    for (int c = 0; c < NCLASS - 1; ++c) {
-        if (!cls_dev && !cls_counts[c]) continue;
-        ScopedTimer tm(ctx, s, KID_RESOLVE0 + c);
-        launch_resolve_class(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap,
-                             cls_dev ? 0u : (uint32_t)cls_counts[c], cls_dev ? cls_dev + c : nullptr, ctx->t_sort, a,
-                             s);
+// The class lists of pass k with their sizes in device memory.
+ResolveWork pass_work(hexfc_ctx *ctx, int k) {
+    ResolveWork w;
+    for (int c = 0; c < NCLASS; ++c) {
+        w.list[c] = ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap;
+        w.n_host[c] = 0;
     }
+    w.n_dev = ctx->stats.as<uint64_t>() + ST_PCLASS + k * NCLASS;
+    return w;
 }
 
-// Silhouettes: the boundary depth of the tiles [g0, g1) of the current lists,
-// and the white overlay once every pass has been resolved.
-void boundary_depth(hexfc_ctx *ctx, int64_t g0, int64_t g1, int64_t pass_p0, hipStream_t s) {
-    launch_boundary_depth(ctx->tl, g0, g1, ctx->views.as<ViewParams>(), ctx->count.as<uint32_t>(),
-                          ctx->off.as<uint64_t>(), pass_p0, ctx->ws, ctx->ws_bytes / 8, ctx->face_bnd.as<uint8_t>(),
+void enqueue_resolve(hexfc_ctx *ctx, const ResolveWork &w, const ResolveArgs &a, hipStream_t s) {
+    ScopedTimer tm(ctx, s, KID_RESOLVE);
+    launch_resolve(w, ctx->t_sort, ctx->res_grid, a, s);
+}
+
+void enqueue_fill(hexfc_ctx *ctx, int nv, int k, hipStream_t s) {
+    ScopedTimer tm(ctx, s, KID_FILL);
+    launch_fill(ctx->tl, nv, pass_tiles(ctx, k), ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
+                ctx->fscr.as<int4>(), ctx->F, ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8,
+                ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
+}
+
+// Silhouettes: the boundary depth of pass k's tiles of the current lists, and
+// the white overlay once every pass has been resolved.
+void boundary_depth(hexfc_ctx *ctx, int nv, int k, hipStream_t s) {
+    launch_boundary_depth(ctx->tl, nv, pass_tiles(ctx, k), ctx->views.as<ViewParams>(), ctx->count.as<uint32_t>(),
+                          ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8, ctx->face_bnd.as<uint8_t>(),
                           ctx->bdepth.as<uint32_t>(), s);
 }
 void silhouettes(hexfc_ctx *ctx, int nv, float *rgba, hipStream_t s) {
     launch_silhouette(ctx->tl, nv, ctx->views.as<ViewParams>(), ctx->bdepth.as<uint32_t>(), rgba, s);
 }
 
-void timed_fill(hexfc_ctx *ctx, int64_t g0, int64_t g1, hipStream_t s) {
-    ScopedTimer tm(ctx, s, KID_FILL);
-    launch_fill(ctx->tl, g0, g1, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(), ctx->bin_cap,
-                ctx->fscr.as<int4>(), ctx->F, ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8,
-                ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), s);
+void finish(hexfc_ctx *ctx, int passes, bool single, hipStream_t s) {
+    launch_finish(ctx->stats.as<uint64_t>(), ctx->persist.as<uint64_t>(), ctx->d_pub, ctx->bin_cap, passes,
+                  ctx->ws_bytes / 8, single, s);
+}
+
+// Grows the triangle bins and the number of screen passes launched per
+// frame to the largest needs the device has reported so far (host-mapped
+// counters of finished frames; nothing waits for the frames in flight).
+hexfc_status grow_from_published(hexfc_ctx *ctx, const Tiling &tl) {
+    const uint64_t bins = ctx->h_pub[1 + PS_MAX_BINS], passes = ctx->h_pub[1 + PS_MAX_PASSES];
+    if (bins > ctx->bin_cap) {  // (the replaced buffers stay allocated for the frames in flight)
+        const uint64_t cap = bins + bins / 4 + 65536;
+        TRY(grow(ctx, ctx->bins, sizeof(uint32_t) * cap));
+        TRY(grow(ctx, ctx->masks, sizeof(uint64_t) * cap * (tl.TW * tl.TH / 64)));
+        ctx->bin_cap = cap;
+    }
+    if (passes > (uint64_t)ctx->passes_launch) ctx->passes_launch = (int)std::min<uint64_t>(passes, MAX_PASSES);
+    return HEXFC_OK;
+}
+
+// Disables the per-launch event timing while a stream is being captured.
+struct NoTimingInCapture {
+    hexfc_ctx *ctx;
+    bool saved;
+    NoTimingInCapture(hexfc_ctx *c, bool cap) : ctx(c), saved(c->prof) {
+        if (cap) ctx->prof = false;
+    }
+    ~NoTimingInCapture() { ctx->prof = saved; }
+};
+
+// Host-known class sizes of the last built lists (the learned and
+// approximate resolves size their launches with them): waits for them when
+// the lists came from a frame that did not read them back.
+hexfc_status need_stats(hexfc_ctx *ctx, hipStream_t s) {
+    if (!ctx->stats_known) TRY(read_stats(ctx, s));
+    return HEXFC_OK;
 }
 
 }  // namespace
@@ -309,15 +384,19 @@ hexfc_status hexfc_build_fragment_lists(hexfc_ctx *ctx, const hexfc_camera *cam,
                                         void *stream) {
     if (!ctx) return HEXFC_EINVAL;
     if (!ctx->ws) FAIL(ctx, HEXFC_ESTATE, "no workspace set");
+    if (!cam) FAIL(ctx, HEXFC_EINVAL, "null camera");
     hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) FAIL(ctx, HEXFC_ESTATE, "hexfc_build_fragment_lists waits for the stream: not in a capture");
+    ctx->last_stream = s;
     ctx->lists_valid = false;
-    TRY(prepare(ctx, 1, cam, s, false));
+    TRY(prepare(ctx, 1, cam, s, FRONT_SINGLE));
     const Tiling &tl = ctx->tl;
     if (ctx->last_stats[ST_FRAGS] * 8 > ctx->ws_bytes)
         FAIL(ctx, HEXFC_EOVERFLOW, "%llu fragments exceed the workspace (%zu bytes)",
              (unsigned long long)ctx->last_stats[ST_FRAGS], ctx->ws_bytes);
-    timed_fill(ctx, 0, tl.ntiles, s);
+    enqueue_fill(ctx, 1, 0, s);
     if (counts_out) launch_rowmajor_counts(tl, ctx->count.as<uint32_t>(), counts_out, s);
+    finish(ctx, 1, true, s);
     HIPCHK(ctx, hipGetLastError());
     ctx->lists_valid = true;
     return HEXFC_OK;
@@ -328,16 +407,15 @@ hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
     if (!ctx) return HEXFC_EINVAL;
     if (!ctx->lists_valid) FAIL(ctx, HEXFC_ESTATE, "no fragment lists built");
     TRY(check_shading(ctx, hot, style, rgba_out));
-    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
-        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    NoTimingInCapture nt(ctx, capturing(s));
+    ctx->last_stream = s;
     shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(upload_views(ctx, 1, s));
-    ResolveArgs a = resolve_args(ctx, rgba_out);
-    launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
+    TRY(set_views(ctx, 1, s));
+    enqueue_resolve(ctx, pass_work(ctx, 0), resolve_args(ctx, rgba_out, 0), s);
     if (style->sil_alpha > 0.f) {
-        boundary_depth(ctx, 0, ctx->tl.ntiles, 0, s);
+        boundary_depth(ctx, 1, 0, s);
         silhouettes(ctx, 1, rgba_out, s);
     }
     HIPCHK(ctx, hipGetLastError());
@@ -351,13 +429,15 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
     TRY(check_shading(ctx, hot, style, rgba_out));
     if (method != HEXFC_APPROX_MLAB && method != HEXFC_APPROX_MOMENTS) FAIL(ctx, HEXFC_EINVAL, "unknown method %d", method);
     if (method == HEXFC_APPROX_MLAB && (k < 1 || k > 8)) FAIL(ctx, HEXFC_ERANGE, "MLAB layers must be in [1, 8]");
-    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
-        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    TRY(need_stats(ctx, s));
+    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
+        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(upload_views(ctx, 1, s));
-    ResolveArgs a = resolve_args(ctx, rgba_out);
+    TRY(set_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, rgba_out, 0);
     if (method == HEXFC_APPROX_MLAB) {  // scratch for the shaded fragments, laid out like the records
         const uint64_t nf = std::min<uint64_t>(ctx->last_stats[ST_FRAGS], ctx->ws_bytes / 8);
         TRY(grow(ctx, ctx->mlab_c, sizeof(float4) * std::max<uint64_t>(nf, 1)));
@@ -379,49 +459,63 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
     Mat3q M;
     TRY(check_camera(ctx, cam, M));  // camera limits first (ERANGE)
     TRY(check_shading(ctx, hot, style, rgba_out));
+    TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    const bool cap = capturing(s);
+    NoTimingInCapture nt(ctx, cap);
+    ctx->last_stream = s;
     ctx->lists_valid = false;
+    ctx->stats_known = false;
     if (ctx->h_views.empty()) ctx->h_views.resize(1);
     shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(prepare(ctx, 1, cam, s, true));
-    const Tiling &tl = ctx->tl;
-    const uint64_t *S = ctx->last_stats;
-    if (S[ST_PLAN_ERR])
-        FAIL(ctx, HEXFC_EOVERFLOW, "one screen tile's fragments exceed the workspace (or > %d passes)", MAX_PASSES);
-    if (S[ST_CLASS + NCLASS - 1]) FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
-    const int npass = (int)S[ST_NPASS];
-    ResolveArgs a = resolve_args(ctx, rgba_out);
-    const bool sil = style->sil_alpha > 0.f;
-    if (npass <= 1) {
-        timed_fill(ctx, 0, tl.ntiles, s);
-        launch_classes(ctx, a, S + ST_CLASS, nullptr, s);
-        if (sil) {
-            boundary_depth(ctx, 0, tl.ntiles, 0, s);
-            silhouettes(ctx, 1, rgba_out, s);
+    const int64_t sig[7] = {cam->width, cam->height, ctx->tw, ctx->th, (int64_t)(uintptr_t)ctx->ws,
+                            (int64_t)ctx->ws_bytes, (int64_t)ctx->mesh_gen};
+    if (memcmp(sig, ctx->frame_sig, sizeof sig) != 0) {
+        // new mesh, viewport, tiling or workspace: forget the sizes learned so far
+        memcpy(ctx->frame_sig, sig, sizeof sig);
+        ctx->sized = false;
+        ctx->passes_launch = 1;
+        if (!cap) {
+            launch_zero_u64(ctx->persist.as<uint64_t>(), PS_COUNT, s);
+            for (int i = 0; i <= PS_COUNT; ++i) ctx->h_pub[i] = 0;
         }
-        HIPCHK(ctx, hipGetLastError());
-        ctx->lists_valid = true;
-        return HEXFC_OK;
     }
-    // several screen passes: each pass fills and resolves a range of tiles
-    uint64_t bounds[MAX_PASSES + 1];
-    for (int i = 0; i <= npass; ++i) bounds[i] = S[ST_PASS + i];
-    uint64_t *stats = ctx->stats.as<uint64_t>();
-    for (int k = 0; k < npass; ++k) {
-        const int64_t t0 = (int64_t)bounds[k], t1 = (int64_t)bounds[k + 1];
-        launch_zero_u64(stats + ST_CLASS, 2 * NCLASS, s);
-        launch_classify(tl, t0, t1, ctx->count.as<uint32_t>(), ctx->t_sort, ctx->cls.as<uint32_t>(), ctx->cls_cap,
-                        stats, s);
-        TRY(read_stats(ctx, s));
-        timed_fill(ctx, t0, t1, s);
-        a.pass_p0 = t0 * tl.TW * tl.TH;
-        launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
-        if (sil) boundary_depth(ctx, t0, t1, a.pass_p0, s);
-        HIPCHK(ctx, hipGetLastError());
+    if (!ctx->sized) {
+        // The first frame of a mesh, viewport, tiling and workspace waits once
+        // for its statistics: bin and list sizes, screen passes.
+        if (cap)
+            FAIL(ctx, HEXFC_ESTATE,
+                 "render one frame of this mesh, viewport, tiling and workspace before capturing one");
+        TRY(prepare(ctx, 1, cam, s, FRONT_PLAN));
+        const uint64_t *S = ctx->last_stats;
+        if (S[ST_PLAN_ERR])
+            FAIL(ctx, HEXFC_EOVERFLOW, "one screen tile's fragments exceed the workspace (or > %d passes)", MAX_PASSES);
+        ctx->passes_launch = (int)std::max<uint64_t>(1, S[ST_NPASS]);
+        ctx->sized = true;
+        ctx->stats_known = false;  // (the pass classes are not in last_stats)
+    } else {
+        if (!cap) TRY(grow_from_published(ctx, ctx->tl));
+        TRY(check_views(ctx, 1, cam));
+        TRY(set_views(ctx, 1, s));
+        enqueue_front(ctx, 1, ctx->tl, s, FRONT_PLAN);
+        ctx->nv = 1;
+        ctx->have_frame = true;
+    }
+    // the passes, whose tile ranges the device planned: passes beyond the
+    // planned number find an empty range and return at once
+    const bool sil = style->sil_alpha > 0.f;
+    for (int k = 0; k < ctx->passes_launch; ++k) {
+        enqueue_classify(ctx, 1, k, s);
+        enqueue_fill(ctx, 1, k, s);
+        enqueue_resolve(ctx, pass_work(ctx, k), resolve_args(ctx, rgba_out, k), s);
+        if (sil) boundary_depth(ctx, 1, k, s);
     }
     if (sil) silhouettes(ctx, 1, rgba_out, s);
+    finish(ctx, ctx->passes_launch, false, s);
     HIPCHK(ctx, hipGetLastError());
-    ctx->last_stats[ST_NPASS] = (uint64_t)npass;
+    // one launched pass: the whole frame's lists are in the workspace (or the
+    // frame is flagged) and hexfc_resolve / the parity export may follow
+    ctx->lists_valid = ctx->passes_launch == 1;
     return HEXFC_OK;
 }
 
@@ -433,6 +527,7 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
     if (ctx->V == 0) FAIL(ctx, HEXFC_ESTATE, "no mesh uploaded");
     TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
     if ((int)ctx->h_views.size() < n) ctx->h_views.resize(n);
     for (int v = 0; v < n; ++v) {
         TRY(check_camera(ctx, &cams[v], ctx->h_views[v].M));
@@ -443,23 +538,24 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
         depth_range(ctx, &cams[v], ctx->h_views[v]);
     }
     ctx->lists_valid = false;
+    ctx->stats_known = false;
     BatchGraph &g = ctx->bg;
     const bool reuse = g.exec && g.nv == n && g.W == cams[0].width && g.H == cams[0].height && g.tw == ctx->tw &&
                        g.th == ctx->th && g.t_sort == ctx->t_sort && g.ws == ctx->ws && g.ws_bytes == ctx->ws_bytes &&
                        g.bin_cap == ctx->bin_cap && g.rgba == rgba_out;
     if (reuse) {
-        TRY(upload_views(ctx, n, s));
+        TRY(set_views(ctx, n, s));
         HIPCHK(ctx, hipGraphLaunch(g.exec, s));
         return HEXFC_OK;
     }
     g.reset();
+    if (capturing(s)) FAIL(ctx, HEXFC_ESTATE, "the first call for a batch shape waits for the stream: not in a capture");
     // sizing pass (synchronous), then capture the whole batch as one graph
-    TRY(prepare(ctx, n, cams, s, false));
+    TRY(prepare(ctx, n, cams, s, FRONT_SINGLE));
     const uint64_t *S = ctx->last_stats;
     if (S[ST_FRAGS] * 8 > ctx->ws_bytes)
         FAIL(ctx, HEXFC_EOVERFLOW, "%llu fragments exceed the workspace (%zu bytes)", (unsigned long long)S[ST_FRAGS],
              ctx->ws_bytes);
-    if (S[ST_CLASS + NCLASS - 1]) FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     {  // headroom for other cameras of the same batch shape
         const uint64_t cap = S[ST_BINS] + S[ST_BINS] / 2 + 65536;
         if (cap > ctx->bin_cap) {
@@ -474,15 +570,13 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
     HIPCHK(ctx, hipStreamSynchronize(s));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        enqueue_front(ctx, n, ctx->tl, cs, false);
-        launch_fill(ctx->tl, 0, (int64_t)ctx->tl.ntiles * n, ctx->tile_off.as<uint64_t>(), ctx->bins.as<uint32_t>(),
-                    ctx->bin_cap, ctx->fscr.as<int4>(), ctx->F, ctx->off.as<uint64_t>(), ctx->ws, ctx->ws_bytes / 8,
-                    ctx->masks.as<uint64_t>(), ctx->gpre.as<uint32_t>(), cs);
-        ResolveArgs a = resolve_args(ctx, rgba_out);
-        launch_classes(ctx, a, nullptr, ctx->stats.as<uint64_t>() + ST_CLASS, cs);
+        enqueue_front(ctx, n, ctx->tl, cs, FRONT_SINGLE);
+        enqueue_fill(ctx, n, 0, cs);
+        enqueue_resolve(ctx, pass_work(ctx, 0), resolve_args(ctx, rgba_out, 0), cs);
         // silhouettes (the kernels skip the views whose sil_alpha is 0)
-        boundary_depth(ctx, 0, (int64_t)ctx->tl.ntiles * n, 0, cs);
+        boundary_depth(ctx, n, 0, cs);
         silhouettes(ctx, n, rgba_out, cs);
+        finish(ctx, 1, true, cs);
         e = hipStreamEndCapture(cs, &g.graph);
     }
     ctx->prof = prof;
@@ -517,21 +611,24 @@ hexfc_status hexfc_batch_status(hexfc_ctx *ctx, uint64_t *fragments, int *overfl
     const uint64_t *S = ctx->last_stats;
     ctx->last_frags = S[ST_FRAGS];
     if (fragments) *fragments = S[ST_FRAGS];
-    if (overflow)
-        *overflow = (S[ST_BINS] > ctx->bin_cap || S[ST_FRAGS] * 8 > ctx->ws_bytes || S[ST_CLASS + NCLASS - 1]) ? 1 : 0;
+    if (overflow) *overflow = S[ST_FLAGS] ? 1 : 0;
     return HEXFC_OK;
 }
 
 hexfc_status hexfc_get_total_fragments(hexfc_ctx *ctx, uint64_t *out) {
     if (!ctx || !out) return HEXFC_EINVAL;
     if (!ctx->have_frame) FAIL(ctx, HEXFC_ESTATE, "no frame built");
-    *out = ctx->last_frags;
+    TRY(set_device(ctx));
+    TRY(read_stats(ctx, ctx->last_stream));
+    *out = ctx->last_stats[ST_FRAGS];
     return HEXFC_OK;
 }
 
 hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n) {
     if (!ctx || !out || n < 0) return HEXFC_EINVAL;
     if (!ctx->have_frame) FAIL(ctx, HEXFC_ESTATE, "no frame built");
+    TRY(set_device(ctx));
+    TRY(read_stats(ctx, ctx->last_stream));
     for (int i = 0; i < n && i < ST_COUNT; ++i) out[i] = ctx->last_stats[i];
     return HEXFC_OK;
 }
@@ -540,19 +637,18 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
                                        void *stream) {
     if (!ctx || !counts_out || !off_out || !rec_out) return HEXFC_EINVAL;
     if (!ctx->lists_valid || ctx->nv != 1) FAIL(ctx, HEXFC_ESTATE, "no single-view fragment lists built");
-    if (ctx->last_stats[ST_CLASS + NCLASS - 1])
-        FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
     const Tiling &tl = ctx->tl;
     const int64_t n = (int64_t)tl.W * tl.H;
     launch_rowmajor_counts(tl, ctx->count.as<uint32_t>(), counts_out, s);
     HIPCHK(ctx, ctx->count_rm_tmp.ensure(sizeof(uint64_t) * scan_tmp_elems(n)));
     launch_scan_u32_u64(counts_out, n, off_out, ctx->count_rm_tmp.as<uint64_t>(), nullptr, s);
-    ResolveArgs a = resolve_args(ctx, nullptr);
+    ResolveArgs a = resolve_args(ctx, nullptr, 0);
     a.sorted_out = rec_out;
     a.off_rm = off_out;
-    launch_classes(ctx, a, ctx->last_stats + ST_CLASS, nullptr, s);
+    enqueue_resolve(ctx, pass_work(ctx, 0), a, s);
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }
@@ -576,6 +672,8 @@ hexfc_status learned_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexf
     if (style->lens_mode != 0)
         FAIL(ctx, HEXFC_EINVAL, "the learned tail's proxy features are defined for the object-space lens");
     if (K < 1 || K > 64) FAIL(ctx, HEXFC_ERANGE, "K must be in [1, 64]");
+    TRY(set_device(ctx));
+    TRY(need_stats(ctx, ctx->last_stream));
     if (ctx->last_stats[ST_CLASS + NCLASS - 1])
         FAIL(ctx, HEXFC_EOVERFLOW, "a pixel list exceeds %d fragments", MAX_LIST);
     return HEXFC_OK;
@@ -602,6 +700,7 @@ hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, co
                                     float *head_out, float *feat_out, float *target_out, uint32_t *pix_out,
                                     int64_t cap, int64_t *rows_out, void *stream) {
     if (!ctx || !rows_out) return HEXFC_EINVAL;
+    if (stream) ctx->last_stream = (hipStream_t)stream;
     TRY(learned_checks(ctx, hot, style, K));
     const int64_t rows = learned_rows(ctx);
     *rows_out = rows;
@@ -609,11 +708,10 @@ hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, co
     if (!head_out || !feat_out || !pix_out) FAIL(ctx, HEXFC_EINVAL, "null output");
     if (cap < rows) FAIL(ctx, HEXFC_EOVERFLOW, "%lld rows exceed the output capacity %lld", (long long)rows,
                          (long long)cap);
-    TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(upload_views(ctx, 1, s));
-    ResolveArgs a = resolve_args(ctx, nullptr);
+    TRY(set_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, nullptr, 0);
     enqueue_tail_features(ctx, a, K, head_out, feat_out, target_out, pix_out, true, s);
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
@@ -623,10 +721,10 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
                                    const float *params, int K, float conf_min, float *rgba_out, uint8_t *mask_out,
                                    void *stream) {
     if (!ctx) return HEXFC_EINVAL;
+    if (stream) ctx->last_stream = (hipStream_t)stream;
     TRY(learned_checks(ctx, hot, style, K));
     if (!params || !rgba_out) FAIL(ctx, HEXFC_EINVAL, "null parameters or output");
     if (!(conf_min >= 0.f && conf_min < 1.f)) FAIL(ctx, HEXFC_ERANGE, "conf_min must be in [0, 1)");
-    TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     const Tiling &tl = ctx->tl;
     const int64_t rows = learned_rows(ctx);
@@ -635,15 +733,16 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
     TRY(grow(ctx, ctx->l_pix, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_fb, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
     shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(upload_views(ctx, 1, s));
-    ResolveArgs a = resolve_args(ctx, rgba_out);
+    TRY(set_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, rgba_out, 0);
     uint64_t *stats = ctx->stats.as<uint64_t>();
     if (mask_out) launch_fill_u8(mask_out, (int64_t)tl.W * tl.H, 1, s);
     launch_zero_u64(stats + ST_FB, NCLASS, s);
     if (ctx->last_stats[ST_CLASS]) {  // short lists: exact
-        ScopedTimer tm(ctx, s, KID_RESOLVE0);
-        launch_resolve_class(0, ctx->cls.as<uint32_t>(), (uint32_t)ctx->last_stats[ST_CLASS], nullptr, ctx->t_sort, a,
-                             s);
+        ResolveWork w{};
+        w.list[0] = ctx->cls.as<uint32_t>();
+        w.n_host[0] = (uint32_t)ctx->last_stats[ST_CLASS];
+        enqueue_resolve(ctx, w, a, s);
     }
     if (rows) {
         float *head = ctx->l_head.as<float>(), *feat = ctx->l_feat.as<float>();
@@ -655,12 +754,14 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
         }
         // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
         ScopedTimer tm(ctx, s, KID_FALLBACK);
+        ResolveWork w{};
         int64_t base = 0;
         for (int c = 1; c < NCLASS - 1; ++c) {
-            const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
-            if (nc) launch_resolve_class(c, fb + base, nc, nullptr, ctx->t_sort, a, s);
-            base += nc;
+            w.list[c] = fb + base;
+            w.n_host[c] = (uint32_t)ctx->last_stats[ST_CLASS + c];
+            base += w.n_host[c];
         }
+        launch_resolve(w, ctx->t_sort, ctx->res_grid, a, s);
     }
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;

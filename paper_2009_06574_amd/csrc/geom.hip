@@ -525,7 +525,8 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
 constexpr int FILL_WINDOW = 512;  // fragments expanded at a time per group (fewer than candidates: LDS for occupancy)
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const uint64_t *__restrict__ tile_off,
+__global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, const uint64_t *__restrict__ pass_tiles,
+                                                    const uint64_t *__restrict__ tile_off,
                                                     const uint32_t *__restrict__ bins,
                                                     const int4 *__restrict__ fscr, int64_t F,
                                                     const uint64_t *__restrict__ off, uint64_t *__restrict__ rec,
@@ -541,8 +542,10 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, int64_t g0, const
     __shared__ uint32_t s_wsum[S][NW];  // per wave: fragments (scan carry)
     __shared__ uint16_t s_frag[S][FILL_WINDOW];
     __shared__ uint64_t s_first[NT];
-    const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
+    const int64_t g0 = (int64_t)pass_tiles[0], g1 = (int64_t)pass_tiles[1];
     const int64_t g = g0 + blockIdx.x;  // global tile
+    if (g >= g1) return;  // (uniform) outside this pass
+    const int grp = threadIdx.x / NT, t = threadIdx.x % NT;
     const int64_t view = g / tl.ntiles;
     const int tile = (int)(g - view * tl.ntiles);
     fscr += view * 4 * F;
@@ -750,6 +753,58 @@ void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, ui
     k_plan<<<1, 64, 0, s>>>(tl.ntiles, tl.TW * tl.TH, off, budget_recs, stats);
 }
 
+__global__ void k_single_pass(int64_t ntiles, uint64_t *__restrict__ stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    stats[ST_NPASS] = 1;
+    stats[ST_PASS] = 0;
+    stats[ST_PASS + 1] = (uint64_t)ntiles;
+}
+
+void launch_single_pass(int64_t ntiles, uint64_t *stats, hipStream_t s) { k_single_pass<<<1, 64, 0, s>>>(ntiles, stats); }
+
+// ------------------------------------------------------------------ closing kernel of a frame
+// Flags what went wrong (the frame's output is then invalid), keeps the
+// largest needs seen across frames and copies them to host-mapped memory, so
+// that the host can size later frames without waiting on this one.  One thread.
+__global__ void k_finish(uint64_t *__restrict__ stats, uint64_t *__restrict__ persist,
+                         volatile uint64_t *__restrict__ published, uint64_t bin_cap, int passes_launched,
+                         uint64_t ws_recs, int single_pass) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t flags = 0;
+    if (stats[ST_BINS] > bin_cap) flags |= FRAME_BINS;
+    if (single_pass) {
+        if (stats[ST_FRAGS] > ws_recs) flags |= FRAME_WORKSPACE;
+    } else if (stats[ST_PLAN_ERR]) {
+        flags |= FRAME_PLAN;
+    } else if (stats[ST_NPASS] > (uint64_t)passes_launched) {
+        flags |= FRAME_PASSES;
+    }
+    stats[ST_FLAGS] = flags;
+    persist[PS_MAX_BINS] = max(persist[PS_MAX_BINS], stats[ST_BINS]);
+    persist[PS_MAX_PASSES] = max(persist[PS_MAX_PASSES], stats[ST_NPASS]);
+    persist[PS_FRAMES] += 1;
+    persist[PS_FLAGGED] += flags ? 1 : 0;
+    persist[PS_LAST_FLAGS] = flags;
+    persist[PS_LAST_FRAGS] = stats[ST_FRAGS];
+    if (published) {
+        for (int i = 0; i < PS_COUNT; ++i) published[1 + i] = persist[i];
+        __threadfence_system();
+        published[0] = persist[PS_FRAMES];
+        __threadfence_system();
+    }
+}
+
+void launch_finish(uint64_t *stats, uint64_t *persist, uint64_t *published, uint64_t bin_cap, int passes_launched,
+                   uint64_t ws_recs, bool single_pass, hipStream_t s) {
+    k_finish<<<1, 64, 0, s>>>(stats, persist, published, bin_cap, passes_launched, ws_recs, single_pass ? 1 : 0);
+}
+
+__global__ void k_set_view(ViewParams vp, ViewParams *__restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = vp;
+}
+
+void launch_set_view(const ViewParams &vp, ViewParams *dst, hipStream_t s) { k_set_view<<<1, 64, 0, s>>>(vp, dst); }
+
 // ------------------------------------------------------------------ length classes
 // Each block classifies CLS_PPT * 256 consecutive pixels (coalesced rows of
 // 256).  Class counts are aggregated per wave (lanes of one class take one
@@ -757,12 +812,14 @@ void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, ui
 // and block: the class counters are the most contended addresses of the frame.
 constexpr int CLS_PPT = 8;
 
-__global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t p1,
-                                                  const uint32_t *__restrict__ count, int t_sort,
+__global__ void __launch_bounds__(256) k_classify(Tiling tl, int k, const uint32_t *__restrict__ count, int t_sort,
                                                   uint32_t *__restrict__ lists, int64_t cap,
                                                   uint64_t *__restrict__ stats) {
     __shared__ unsigned s_n[NCLASS];
     __shared__ unsigned long long s_f[NCLASS], s_base[NCLASS];
+    const int64_t TPX = (int64_t)tl.TW * tl.TH;
+    const int64_t p0 = (int64_t)stats[ST_PASS + k] * TPX, p1 = (int64_t)stats[ST_PASS + k + 1] * TPX;
+    if (p0 + (int64_t)blockIdx.x * (256 * CLS_PPT) >= p1) return;  // (uniform) outside this pass
     if (threadIdx.x < NCLASS) {
         s_n[threadIdx.x] = 0;
         s_f[threadIdx.x] = 0;
@@ -817,7 +874,10 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
     __syncthreads();
     if (threadIdx.x < NCLASS) {
         const int c = threadIdx.x;
-        s_base[c] = s_n[c] ? atomicAdd((unsigned long long *)&stats[ST_CLASS + c], (unsigned long long)s_n[c]) : 0ull;
+        s_base[c] = s_n[c] ? atomicAdd((unsigned long long *)&stats[ST_PCLASS + k * NCLASS + c],
+                                       (unsigned long long)s_n[c])
+                           : 0ull;
+        if (s_n[c]) atomicAdd((unsigned long long *)&stats[ST_CLASS + c], (unsigned long long)s_n[c]);
         if (s_f[c]) atomicAdd((unsigned long long *)&stats[ST_CLASSF + c], s_f[c]);
     }
     __syncthreads();
@@ -826,15 +886,12 @@ __global__ void __launch_bounds__(256) k_classify(Tiling tl, int64_t p0, int64_t
         if (cls[i] >= 0) lists[(int64_t)cls[i] * cap + s_base[cls[i]] + rank[i]] = (uint32_t)(blk0 + i * 256 + threadIdx.x);
 }
 
-void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *count, int t_sort,
-                     uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s) {
-    const int TP = tl.TW * tl.TH;
-    int64_t p0 = g0 * TP, p1 = g1 * TP;
-    int64_t n = p1 - p0;
+void launch_classify(const Tiling &tl, int nv, int k, const uint32_t *count, int t_sort, uint32_t *cls_lists,
+                     int64_t cls_cap, uint64_t *stats, hipStream_t s) {
+    const int64_t n = (int64_t)tl.ntiles * nv * tl.TW * tl.TH;
     if (n <= 0) return;
     const int64_t per = 256 * CLS_PPT;
-    k_classify<<<dim3((unsigned)((n + per - 1) / per)), 256, 0, s>>>(tl, p0, p1, count, t_sort, cls_lists, cls_cap,
-                                                                     stats);
+    k_classify<<<dim3((unsigned)((n + per - 1) / per)), 256, 0, s>>>(tl, k, count, t_sort, cls_lists, cls_cap, stats);
 }
 
 // ------------------------------------------------------------------ small utilities
@@ -912,12 +969,13 @@ void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint
 #undef ARGS
 }
 
-void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec, uint64_t rec_cap,
-                 const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
-    if (g1 <= g0) return;
-    dim3 g((unsigned)(g1 - g0));
-#define ARGS tl, g0, tile_off, bins, fscr, F, off, rec, rec_cap, cap, masks, gpre
+void launch_fill(const Tiling &tl, int nv, const uint64_t *pass_tiles, const uint64_t *tile_off,
+                 const uint32_t *bins, uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec,
+                 uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s) {
+    const int64_t nt = (int64_t)tl.ntiles * nv;
+    if (nt <= 0) return;
+    dim3 g((unsigned)nt);
+#define ARGS tl, pass_tiles, tile_off, bins, fscr, F, off, rec, rec_cap, cap, masks, gpre
     HEXFC_TILE_DISPATCH(8, 8, (k_fill<8, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 8, (k_fill<16, 8><<<g, RASTER_WG, 0, s>>>(ARGS)));
     HEXFC_TILE_DISPATCH(16, 16, (k_fill<16, 16><<<g, RASTER_WG, 0, s>>>(ARGS)));

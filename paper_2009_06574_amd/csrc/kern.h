@@ -18,33 +18,53 @@ constexpr int64_t GUARD = int64_t(1) << 17;     // |s| >= GUARD culls
 constexpr int64_t QNUM = int64_t(1) << 56;      // q = floor(QNUM / w_q)
 constexpr uint32_t KMAX = 1u << 24;             // depth field = KMAX - key
 constexpr int MAX_PASSES = 64;
-constexpr int MAX_LIST = 2048;                  // longest list a resolve kernel sorts
+constexpr int MAX_LIST = 2048;                  // longest list the learned and approximate resolves take
 
-// length classes of the resolve: 0 = short (lane per pixel, n <= t_sort), then
-// wave-per-pixel bitonic sorts of 64, 128, 256, 512, 1024, 2048 padded
-// elements (classes 1..6); class 7 = longer than MAX_LIST (an error).
+// length classes: 0 = short (lane per pixel, n <= t_sort), 1..3 = up to 64,
+// 128, 256 fragments (wave per pixel, bitonic sort in registers), 4..6 = up to
+// 512, 1024, 2048 (workgroup per pixel, bitonic sort in LDS), 7 = longer
+// (workgroup per pixel, sorted in place in the workspace).
 constexpr int NCLASS = 8;
 
-// device-side statistics written by the kernels (read back by the host)
+// device-side statistics written by the kernels (zeroed at the start of every
+// frame; read back by the host only where an entry point says it waits)
 enum StatSlot {
     ST_BINS = 0,      // bin entries needed
     ST_FRAGS = 1,     // total fragments
     ST_NPASS = 2,     // passes planned
-    ST_PLAN_ERR = 3,  // a single tile exceeds the workspace
-    ST_CLASS = 8,     // NCLASS class sizes (pixels)
-    ST_CLASSF = 16,   // NCLASS class sizes (fragments)
+    ST_PLAN_ERR = 3,  // a single tile exceeds the workspace (or more than MAX_PASSES passes)
+    ST_FLAGS = 4,     // FRAME_* flags of the frame (set by the closing kernel)
+    ST_CLASS = 8,     // NCLASS class sizes (pixels), all passes
+    ST_CLASSF = 16,   // NCLASS class sizes (fragments), all passes
     ST_FB = 24,       // NCLASS pixels sent back to the exact resolve by the learned one
-    ST_PASS = 32,     // MAX_PASSES + 1 tile boundaries
-    ST_COUNT = 32 + MAX_PASSES + 1
+    ST_PASS = 32,     // MAX_PASSES + 1 tile boundaries of the passes
+    ST_PCLASS = ST_PASS + MAX_PASSES + 1,  // [MAX_PASSES][NCLASS] class sizes of each pass
+    ST_COUNT = ST_PCLASS + MAX_PASSES * NCLASS
+};
+
+// flags of a frame (ST_FLAGS): its output is invalid when any is set
+enum FrameFlag {
+    FRAME_BINS = 1,       // more triangle-bin entries than the bin buffer holds
+    FRAME_PASSES = 2,     // more screen passes needed than were launched
+    FRAME_PLAN = 4,       // a single screen tile exceeds the workspace, or more than MAX_PASSES passes
+    FRAME_WORKSPACE = 8,  // (single-pass frames) more fragments than the workspace holds
+};
+
+// device-side counters kept across frames (not zeroed per frame): the
+// largest needs seen, so that the host can grow its buffers for later frames
+// without waiting on any of them; copied after every frame into host-mapped
+// memory by the closing kernel
+enum PersistSlot {
+    PS_MAX_BINS = 0, PS_MAX_PASSES, PS_FRAMES, PS_FLAGGED, PS_LAST_FLAGS, PS_LAST_FRAGS, PS_COUNT = 8
 };
 
 // kernels timed by the optional per-launch HIP-event profiler
 enum KernelId {
     KID_TRANSFORM = 0, KID_BIN_COUNT, KID_BIN_SCATTER, KID_COUNT, KID_SCAN, KID_CLASSIFY, KID_PLAN, KID_FILL,
-    KID_RESOLVE0,  // + length class
-    KID_TAIL = KID_RESOLVE0 + NCLASS,  // learned resolve: head and tail features
-    KID_MLP,                           // learned resolve: network and compose
-    KID_FALLBACK,                      // learned resolve: exact fallback
+    KID_RESOLVE,   // the persistent resolve (every length class)
+    KID_TAIL,      // learned resolve: head and tail features
+    KID_MLP,       // learned resolve: network and compose
+    KID_FALLBACK,  // learned resolve: exact fallback
     KID_COUNT_
 };
 
@@ -165,19 +185,34 @@ void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &t
 constexpr int RASTER_WG = 512;
 void launch_count(const Tiling &tl, int nv, const uint64_t *tile_off, const uint32_t *bins, uint64_t cap,
                   const int4 *fscr, int64_t F, uint32_t *count, uint64_t *masks, uint32_t *gpre, hipStream_t s);
-// fill global tiles [g0, g1); records are relative to off[g0 * TP]; at most rec_cap records
-void launch_fill(const Tiling &tl, int64_t g0, int64_t g1, const uint64_t *tile_off, const uint32_t *bins,
-                 uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec, uint64_t rec_cap,
-                 const uint64_t *masks, const uint32_t *gpre, hipStream_t s);
+// fill the tiles [pass_tiles[0], pass_tiles[1]) of one pass (device range; the
+// grid covers the nv views' tiles, workgroups outside the range return);
+// records are relative to off[pass_tiles[0] * TP]; at most rec_cap records
+void launch_fill(const Tiling &tl, int nv, const uint64_t *pass_tiles, const uint64_t *tile_off,
+                 const uint32_t *bins, uint64_t cap, const int4 *fscr, int64_t F, const uint64_t *off, uint64_t *rec,
+                 uint64_t rec_cap, const uint64_t *masks, const uint32_t *gpre, hipStream_t s);
 // exclusive scan of n uint32 values into n+1 uint64 values (out[n] = total);
 // `stat` (nullable) receives the total.  tmp: scan_tmp_elems(n) uint64s.
 size_t scan_tmp_elems(int64_t n);
 void launch_scan_u32_u64(const uint32_t *in, int64_t n, uint64_t *out, uint64_t *tmp, uint64_t *stat,
                          hipStream_t s);
 void launch_plan(const Tiling &tl, const uint64_t *off, uint64_t budget_recs, uint64_t *stats, hipStream_t s);
-// pixels of global tiles [g0, g1) into per-class lists (global pixel ids)
-void launch_classify(const Tiling &tl, int64_t g0, int64_t g1, const uint32_t *count, int t_sort,
-                     uint32_t *cls_lists, int64_t cls_cap, uint64_t *stats, hipStream_t s);
+// one pass over all ntiles tiles (the pass table of a frame that must fit the workspace)
+void launch_single_pass(int64_t ntiles, uint64_t *stats, hipStream_t s);
+// pixels of pass k (tiles stats[ST_PASS + k] .. stats[ST_PASS + k + 1]; the grid
+// covers the nv views' tiles) into per-class lists (global pixel ids); the
+// class sizes go to stats[ST_PCLASS + k NCLASS ...] and are added to the
+// frame totals stats[ST_CLASS ...], stats[ST_CLASSF ...]
+void launch_classify(const Tiling &tl, int nv, int k, const uint32_t *count, int t_sort, uint32_t *cls_lists,
+                     int64_t cls_cap, uint64_t *stats, hipStream_t s);
+// closing kernel of a frame: FRAME_* flags into stats[ST_FLAGS], the largest
+// needs and frame counters into persist[PS_*], and persist copied to the
+// host-mapped `published` (nullable): published[0] = frames finished, then
+// persist[0 .. PS_COUNT - 1] at published[1 ..].
+void launch_finish(uint64_t *stats, uint64_t *persist, uint64_t *published, uint64_t bin_cap, int passes_launched,
+                   uint64_t ws_recs, bool single_pass, hipStream_t s);
+// view parameters by value into device memory (a graph capturing the frame keeps them)
+void launch_set_view(const ViewParams &vp, ViewParams *dst, hipStream_t s);
 void launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_rowmajor_counts(const Tiling &tl, const uint32_t *count_tm, uint32_t *count_rm, hipStream_t s);
@@ -189,19 +224,28 @@ struct ResolveArgs {
     const ViewParams *views;  // [NV]
     const uint32_t *count;    // global tile-major pixels
     const uint64_t *off;
-    const uint64_t *rec;      // workspace (pass-relative)
+    uint64_t *rec;            // workspace (pass-relative); lists longer than 2048 are sorted in place
     uint64_t rec_cap;         // records the workspace holds
-    int64_t pass_p0;          // first global pixel of the pass; records are relative to off[pass_p0]
+    int64_t pass_p0;          // first global pixel of the pass (when pass_tiles is null)
+    const uint64_t *pass_tiles;  // nullable: device [first, end) tiles of the pass; records are
+                                 // relative to off[first * TW * TH] (else to off[pass_p0])
     float *rgba;              // [NV][H][W][4], nullable (sort-only)
     uint64_t *sorted_out;     // nullable: sorted records, row-major CSR (single view)
     const uint64_t *off_rm;   // row-major offsets for sorted_out
 };
-// npix > 0: exact grid for that many pixels.  npix_dev != nullptr: a fixed,
-// persistent grid that reads the class size from device memory (graph replay).
-// Long-list classes (1..6) skip list entries equal to PIX_SKIP.
+// The pixels one resolve launch handles: per length class a list of global
+// pixel ids (entries equal to PIX_SKIP are skipped) and its size, from device
+// memory (n_dev, NCLASS values) or, when n_dev is null, from n_host.
 constexpr uint32_t PIX_SKIP = 0xffffffffu;
-void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
-                          const ResolveArgs &a, hipStream_t s);
+struct ResolveWork {
+    const uint32_t *list[NCLASS];
+    const uint64_t *n_dev;
+    uint32_t n_host[NCLASS];
+};
+// Persistent grid sizes of the resolve for t_sort <= 16, <= 32, <= 64
+// (workgroups the device holds at once).
+void resolve_grids(int device, int grid[3]);
+void launch_resolve(const ResolveWork &w, int t_sort, const int grid[3], const ResolveArgs &a, hipStream_t s);
 
 // Learned tail (resolve.hip): for the pixels of long-list class cls, the exact
 // composite of the first K sorted fragments (head[4]), 9 tail features and,
@@ -214,11 +258,12 @@ void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int 
                           float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
                           int64_t out_base, hipStream_t s);
 
-// Silhouettes of the boundary surface: per pixel of global tiles [g0, g1)
-// the depth key of its nearest fragment of a boundary face (0: none), for the
+// Silhouettes of the boundary surface: per pixel of the pass's tiles
+// (device range pass_tiles[0..1]; the grid covers the nv views' tiles) the
+// depth key of its nearest fragment of a boundary face (0: none), for the
 // views whose sil_a > 0; then white on the silhouette pixels of all views.
-void launch_boundary_depth(const Tiling &tl, int64_t g0, int64_t g1, const ViewParams *views, const uint32_t *count,
-                           const uint64_t *off, int64_t pass_p0, const uint64_t *rec, uint64_t rec_cap,
+void launch_boundary_depth(const Tiling &tl, int nv, const uint64_t *pass_tiles, const ViewParams *views,
+                           const uint32_t *count, const uint64_t *off, const uint64_t *rec, uint64_t rec_cap,
                            const uint8_t *face_bnd, uint32_t *bdepth, hipStream_t s);
 void launch_silhouette(const Tiling &tl, int nv, const ViewParams *views, const uint32_t *bdepth, float *rgba,
                        hipStream_t s);

@@ -12,6 +12,8 @@
 //     lane in registers (cross-lane stages by lane shuffles), every lane
 //     shading its R fragments in parallel, then an ordered wave reduction
 //     with the associative "over" operator.
+#include <algorithm>
+
 #include "kern.h"
 
 namespace hexfc {
@@ -135,58 +137,72 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
 
 constexpr float T_EPS = 9.5367431640625e-07f;  // 2^-20: stop once 1 - A is below it
 
-// ------------------------------------------------------------------ short lists
-// One lane per pixel.  With npix_dev set the grid is persistent: it strides
-// over the class list whose size it reads from device memory.
+// ------------------------------------------------------------------ one persistent resolve
+// Every pixel of a pass is resolved by one persistent launch that takes the
+// lists longest first: the length classes are walked from the longest (a
+// workgroup per pixel) through the medium ones (a wave per pixel) to the
+// short ones (a lane per pixel), and within each phase the items are dealt
+// to the workgroups (or waves) round-robin, so the few very long lists start
+// at once and the many short ones fill in behind them.  The class lists and
+// their sizes come from device memory: nothing about the frame's lists is
+// known to the host when the launch is enqueued.
+
+constexpr int RT = 256;      // threads of the resolve workgroup (4 waves)
+constexpr int LCAP = 2048;   // longest list a workgroup sorts in LDS; longer ones are sorted in place
+
+// Records of a pass are stored relative to the offset of the pass's first pixel.
+__device__ __forceinline__ uint64_t rec_base(const ResolveArgs &a) {
+    const int64_t p0 = a.pass_tiles ? (int64_t)a.pass_tiles[0] * (a.tl.TW * a.tl.TH) : a.pass_p0;
+    return a.off[p0];
+}
+
+__device__ __forceinline__ void write_rgba(const ResolveArgs &a, const PixelRef &pr, const ShadeParams &sp, float C0,
+                                           float C1, float C2, float A) {
+    const float T = 1.f - A;
+    reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
+        make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
+}
+
+// Short list of pixel p (n <= TS): one lane, insertion sort in the lane's LDS
+// column, then a sequential front-to-back blend.
 template <int TS>
-__global__ void __launch_bounds__(64) k_resolve_short(const uint32_t *__restrict__ list, uint32_t npix,
-                                                      const uint64_t *__restrict__ npix_dev, ResolveArgs a) {
-    __shared__ uint64_t col[TS][64];
-    const int lane = threadIdx.x;
-    const uint32_t total = npix_dev ? (uint32_t)*npix_dev : npix;
-    for (uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x); chunk * 64 < total; chunk += gridDim.x) {
-        const uint32_t idx = chunk * 64 + lane;
-        if (idx >= total) continue;
-        const uint32_t p = list[idx];
-        uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
-        const uint64_t first = a.off[p] - a.off[a.pass_p0];
-        if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
-        const uint64_t *src = a.rec + first;
+__device__ __forceinline__ void resolve_lane(const ResolveArgs &a, uint64_t base, uint32_t p,
+                                             uint64_t (*__restrict__ col)[64], int lane) {
+    uint32_t n = min(a.count[p], (uint32_t)TS);  // the class guarantees n <= t_sort <= TS
+    const uint64_t first = a.off[p] - base;
+    if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
+    const uint64_t *src = a.rec + first;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t r = src[i];
+        int j = (int)i;
+        while (j > 0 && col[j - 1][lane] > r) {
+            col[j][lane] = col[j - 1][lane];
+            --j;
+        }
+        col[j][lane] = r;
+    }
+    const PixelRef pr = pixel_ref(a.tl, p);
+    if (a.sorted_out) {
+        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+        for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
+    }
+    if (a.rgba) {
+        const ShadeParams &sp = a.views[pr.view].sp;
+        const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
         for (uint32_t i = 0; i < n; ++i) {
-            const uint64_t r = src[i];
-            int j = (int)i;
-            while (j > 0 && col[j - 1][lane] > r) {
-                col[j][lane] = col[j - 1][lane];
-                --j;
-            }
-            col[j][lane] = r;
-        }
-        const PixelRef pr = pixel_ref(a.tl, p);
-        if (a.sorted_out) {
-            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
-            for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
-        }
-        if (a.rgba) {
-            const ShadeParams &sp = a.views[pr.view].sp;
-            const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
-            float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
-            for (uint32_t i = 0; i < n; ++i) {
-                const float T = 1.f - A;
-                if (T < T_EPS) break;
-                const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(col[i][lane] & 0xffffffffu), pr.x, pr.y);
-                C0 += T * fr.r;
-                C1 += T * fr.g;
-                C2 += T * fr.b;
-                A += T * fr.a;
-            }
             const float T = 1.f - A;
-            float4 out = make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
-            reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = out;
+            if (T < T_EPS) break;
+            const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(col[i][lane] & 0xffffffffu), pr.x, pr.y);
+            C0 += T * fr.r;
+            C1 += T * fr.g;
+            C2 += T * fr.b;
+            A += T * fr.a;
         }
+        write_rgba(a, pr, sp, C0, C1, C2, A);
     }
 }
 
-// ------------------------------------------------------------------ long lists
 // Element e = lane*R + r of the padded list lives in register v[r] of `lane`.
 template <int R, class K>
 __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
@@ -221,6 +237,23 @@ __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
     }
 }
 
+// Ordered wave reduction of premultiplied fragments with the "over"
+// operator: lane l's fragment lies in front of lane l + 1's; lane 0 ends with
+// the composite of the whole wave.
+__device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, float &A, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o), qa = __shfl_down(A, o);
+        if ((lane & (2 * o - 1)) == 0) {
+            const float T = 1.f - A;
+            C0 += T * q0;
+            C1 += T * q1;
+            C2 += T * q2;
+            A += T * qa;
+        }
+    }
+}
+
 // Shade the sorted list of pixel pr in rounds of 64 fragments (element 64k + l
 // to lane l), blend each round with the ordered "over" reduction, and stop
 // once the pixel is opaque to within 2^-20: the fragments behind add less
@@ -248,19 +281,7 @@ __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRe
             c2 = fr.b;
             ca = fr.a;
         }
-        // ordered reduction: lane l's fragment precedes lane l+1's
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const float q0 = __shfl_down(c0, o), q1 = __shfl_down(c1, o), q2 = __shfl_down(c2, o),
-                        qa = __shfl_down(ca, o);
-            if ((lane & (2 * o - 1)) == 0) {
-                const float T = 1.f - ca;
-                c0 += T * q0;
-                c1 += T * q1;
-                c2 += T * q2;
-                ca += T * qa;
-            }
-        }
+        over_reduce(c0, c1, c2, ca, lane);
         c0 = __shfl(c0, 0);
         c1 = __shfl(c1, 0);
         c2 = __shfl(c2, 0);
@@ -272,144 +293,322 @@ __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRe
         A += T * ca;
         if (1.f - A < T_EPS) break;
     }
-    if (lane == 0) {
-        const float T = 1.f - A;
-        float4 out = make_float4(C0 + T * sp.bg[0], C1 + T * sp.bg[1], C2 + T * sp.bg[2], A);
-        reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = out;
-    }
+    if (lane == 0) write_rgba(a, pr, sp, C0, C1, C2, A);
     return true;
 }
 
+// Medium list of pixel p (n <= 64 R): one wave, bitonic sort in registers.
 template <int R>
-__device__ __forceinline__ void resolve_long(const uint32_t *__restrict__ list, uint32_t npix,
-                                             const uint64_t *__restrict__ npix_dev, const ResolveArgs &a) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t total = npix_dev ? (uint32_t)*npix_dev : npix;
-    for (uint32_t blk = xcd_contiguous(blockIdx.x, gridDim.x); blk * 4 < total; blk += gridDim.x) {
-        const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
-        if (wave >= total) continue;
-        const uint32_t p = list[wave];
-        if (p == PIX_SKIP) continue;
-        uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
-        const uint64_t first = a.off[p] - a.off[a.pass_p0];
-        if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
-        const uint64_t *src = a.rec + first;
-        const PixelRef pr = pixel_ref(a.tl, p);
-        if constexpr (R <= 4) {
-            // Rendering only (no sorted export): sort 32-bit keys (depth << 8 |
-            // position in the list; depths stay below 2^24 - 1, so the padding
-            // ~0 sorts last) and keep the triangle ids where they were loaded.
-            // Equal depths must be ordered by triangle id, which these keys do
-            // not hold: the rounds stop short of the first such pair, and a
-            // pixel that needs fragments past it takes the 64-bit sort below.
-            if (!a.sorted_out) {
-                if (!a.rgba) continue;
-                uint32_t key[R], tri[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t e = lane * R + r;
-                    const uint64_t rec = e < n ? src[e] : ~0ull;
-                    key[r] = e < n ? ((uint32_t)(rec >> 32) << 8) | e : ~0u;
-                    tri[r] = (uint32_t)rec;
-                }
-                bitonic_sort<R>(key, lane);
-                // first position e with equal depths at e and e + 1
-                const uint32_t nxt = __shfl_down(key[0], 1);
-                uint32_t tie = ~0u;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
-                    const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
-                    const uint64_t b = __ballot(t);
-                    if (b) tie = min(tie, (uint32_t)__builtin_ctzll(b) * R + r);
-                }
-                const bool done = shade_rounds<R>(a, pr, n, lane, tie, [&](int k) {
-                    const uint32_t e = 64u * k + lane;
-                    uint32_t sk = ~0u;
-#pragma unroll
-                    for (int rr = 0; rr < R; ++rr) {
-                        const uint32_t t = __shfl(key[rr], (int)(e / R));
-                        if ((int)(e % R) == rr) sk = t;
-                    }
-                    const uint32_t idx = sk & 0xffu;
-                    uint32_t tr = 0;
-#pragma unroll
-                    for (int rr = 0; rr < R; ++rr) {
-                        const uint32_t t = __shfl(tri[rr], (int)(idx / R));
-                        if ((int)(idx % R) == rr) tr = t;
-                    }
-                    return tr;
-                });
-                if (done) continue;
-            }
-        }
-        uint64_t v[R];
+__device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint64_t base, uint32_t p, int lane) {
+    uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
+    const uint64_t first = a.off[p] - base;
+    if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
+    const uint64_t *src = a.rec + first;
+    const PixelRef pr = pixel_ref(a.tl, p);
+    // Rendering only (no sorted export): sort 32-bit keys (depth << 8 |
+    // position in the list; depths stay below 2^24 - 1, so the padding ~0
+    // sorts last) and keep the triangle ids where they were loaded.  Equal
+    // depths must be ordered by triangle id, which these keys do not hold: the
+    // rounds stop short of the first such pair, and a pixel that needs
+    // fragments past it takes the 64-bit sort below.
+    if (!a.sorted_out) {
+        if (!a.rgba) return;
+        uint32_t key[R], tri[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t e = lane * R + r;
-            v[r] = e < n ? src[e] : ~0ull;
+            const uint64_t rec = e < n ? src[e] : ~0ull;
+            key[r] = e < n ? ((uint32_t)(rec >> 32) << 8) | e : ~0u;
+            tri[r] = (uint32_t)rec;
         }
-        bitonic_sort<R>(v, lane);
-        if (a.sorted_out) {
-            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+        bitonic_sort<R>(key, lane);
+        // first position e with equal depths at e and e + 1
+        const uint32_t nxt = __shfl_down(key[0], 1);
+        uint32_t tie = ~0u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t e = lane * R + r;
-                if (e < n) dst[e] = v[r];
+        for (int r = 0; r < R; ++r) {
+            const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
+            const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
+            const uint64_t b = __ballot(t);
+            if (b) tie = min(tie, (uint32_t)__builtin_ctzll(b) * R + r);
+        }
+        const bool done = shade_rounds<R>(a, pr, n, lane, tie, [&](int k) {
+            const uint32_t e = 64u * k + lane;
+            uint32_t sk = ~0u;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const uint32_t t = __shfl(key[rr], (int)(e / R));
+                if ((int)(e % R) == rr) sk = t;
             }
-        }
-        if (a.rgba)
-            shade_rounds<R>(a, pr, n, lane, ~0u, [&](int k) {
-                const uint32_t e = 64u * k + lane;
-                uint64_t x = ~0ull;
+            const uint32_t idx = sk & 0xffu;
+            uint32_t tr = 0;
 #pragma unroll
-                for (int rr = 0; rr < R; ++rr) {
-                    const uint64_t t = __shfl(v[rr], (int)(e / R));
-                    if ((int)(e % R) == rr) x = t;
+            for (int rr = 0; rr < R; ++rr) {
+                const uint32_t t = __shfl(tri[rr], (int)(idx / R));
+                if ((int)(idx % R) == rr) tr = t;
+            }
+            return tr;
+        });
+        if (done) return;
+    }
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        v[r] = e < n ? src[e] : ~0ull;
+    }
+    bitonic_sort<R>(v, lane);
+    if (a.sorted_out) {
+        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = lane * R + r;
+            if (e < n) dst[e] = v[r];
+        }
+    }
+    if (a.rgba)
+        shade_rounds<R>(a, pr, n, lane, ~0u, [&](int k) {
+            const uint32_t e = 64u * k + lane;
+            uint64_t x = ~0ull;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const uint64_t t = __shfl(v[rr], (int)(e / R));
+                if ((int)(e % R) == rr) x = t;
+            }
+            return (uint32_t)(x & 0xffffffffu);
+        });
+}
+
+// Ascending compare-exchange of two 64-bit keys at lo < hi.
+__device__ __forceinline__ void cmpx(uint64_t *__restrict__ k, uint32_t lo, uint32_t hi) {
+    const uint64_t x = k[lo], y = k[hi];
+    if (x > y) {
+        k[lo] = y;
+        k[hi] = x;
+    }
+}
+
+// Bitonic sort of N (a power of two, <= LCAP) keys in LDS by the workgroup,
+// ascending.
+__device__ __forceinline__ void block_sort_lds(uint64_t *__restrict__ k, uint32_t N, int tid) {
+    for (uint32_t size = 2; size <= N; size <<= 1)
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = tid; i < N / 2; i += RT) {
+                const uint32_t lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1)), hi = lo + stride;
+                const uint64_t x = k[lo], y = k[hi];
+                const bool up = (lo & size) == 0;
+                if ((x > y) == up) {
+                    k[lo] = y;
+                    k[hi] = x;
                 }
-                return (uint32_t)(x & 0xffffffffu);
-            });
+            }
+            __syncthreads();
+        }
+}
+
+// Half-cleaner stages stride = from .. 1 (ascending) on LDS chunk k of LCAP keys.
+__device__ __forceinline__ void block_half_cleaners_lds(uint64_t *__restrict__ k, uint32_t from, int tid) {
+    for (uint32_t stride = from; stride > 0; stride >>= 1) {
+        for (uint32_t i = tid; i < LCAP / 2; i += RT) {
+            const uint32_t lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
+            cmpx(k, lo, lo + stride);
+        }
+        __syncthreads();
     }
 }
 
-// Up to 8 keys per lane the kernel is held to 96 VGPRs (5 waves per SIMD
-// instead of 4), which measured 2-10% faster per class on the 1080p benchmark
-// frames; the wider sorts keep their registers.
-template <int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
-k_resolve_long(const uint32_t *__restrict__ list, uint32_t npix, const uint64_t *__restrict__ npix_dev, ResolveArgs a) {
-    resolve_long<R>(list, npix, npix_dev, a);
-}
-template <int R>
-__global__ void __launch_bounds__(256)
-k_resolve_long_wide(const uint32_t *__restrict__ list, uint32_t npix, const uint64_t *__restrict__ npix_dev,
-                    ResolveArgs a) {
-    resolve_long<R>(list, npix, npix_dev, a);
+// In-place ascending sort of a list of n > LCAP records in global memory by
+// one workgroup: every LCAP chunk is sorted in LDS, then the sorted runs are
+// merged by the bitonic merge in its ascending-only form (each merge starts by
+// comparing element i of a block with its mirror image, then halves), which
+// never moves an element past the end of the list: elements beyond n count as
+// +infinity and are not touched, so the list needs no padding in memory.
+// Strides of at least LCAP go through global memory (the workgroup owns the
+// list; its barriers order the accesses), shorter ones through LDS chunks.
+// Reordering the records within the list is harmless: every reader sorts.
+__device__ void block_sort_global(uint64_t *__restrict__ g, uint32_t n, uint64_t *__restrict__ lds, int tid) {
+    const uint32_t nch = (n + LCAP - 1) / LCAP;
+    auto load_chunk = [&](uint32_t c) {
+        const uint32_t b = c * LCAP, m = min((uint32_t)LCAP, n - b);
+        for (uint32_t i = tid; i < LCAP; i += RT) lds[i] = i < m ? g[b + i] : ~0ull;
+        __syncthreads();
+        return m;
+    };
+    auto store_chunk = [&](uint32_t c, uint32_t m) {
+        for (uint32_t i = tid; i < m; i += RT) g[c * LCAP + i] = lds[i];
+        __syncthreads();
+    };
+    for (uint32_t c = 0; c < nch; ++c) {
+        const uint32_t m = load_chunk(c);
+        block_sort_lds(lds, LCAP, tid);
+        store_chunk(c, m);
+    }
+    uint32_t N = LCAP;
+    while (N < n) N <<= 1;
+    for (uint32_t size = 2 * LCAP; size <= N; size <<= 1) {
+        const uint32_t h = size >> 1;
+        for (uint32_t i = tid; i < N / 2; i += RT) {  // mirror stage
+            const uint32_t blk = i / h, r = i % h;
+            const uint32_t lo = blk * size + r, hi = blk * size + size - 1 - r;
+            if (hi < n) cmpx(g, lo, hi);
+        }
+        __syncthreads();
+        for (uint32_t stride = size >> 2; stride >= LCAP; stride >>= 1) {
+            for (uint32_t i = tid; i < N / 2; i += RT) {
+                const uint32_t lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1)), hi = lo + stride;
+                if (hi < n) cmpx(g, lo, hi);
+            }
+            __syncthreads();
+        }
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint32_t m = load_chunk(c);
+            block_half_cleaners_lds(lds, LCAP / 2, tid);
+            store_chunk(c, m);
+        }
+    }
 }
 
-// persistent grids: enough blocks to fill the chip several times over
-constexpr unsigned PERSIST_SHORT = 256 * 16, PERSIST_LONG = 256 * 8;
+struct BlockLds {
+    uint64_t keys[LCAP];
+    float4 red[RT / 64];
+};
 
-void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, const uint64_t *npix_dev, int t_sort,
-                          const ResolveArgs &a, hipStream_t s) {
-    if (npix == 0 && !npix_dev) return;
-    if (cls == 0) {
-        dim3 g(npix_dev ? PERSIST_SHORT : (npix + 63) / 64);
-        if (t_sort <= 16) k_resolve_short<16><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
-        else if (t_sort <= 32) k_resolve_short<32><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
-        else k_resolve_short<64><<<g, 64, 0, s>>>(pix_list, npix, npix_dev, a);
-        return;
+// Long list of pixel p (n > 256): one workgroup sorts it (in LDS when it
+// fits, else in place) and shades it in rounds of 256 fragments, the four
+// waves' ordered composites being combined in wave order.
+__device__ void resolve_block(const ResolveArgs &a, uint64_t base, uint32_t p, BlockLds &L, int tid) {
+    uint32_t n = a.count[p];
+    const uint64_t first = a.off[p] - base;
+    if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
+    uint64_t *src = a.rec + first;
+    const bool in_lds = n <= (uint32_t)LCAP;
+    if (in_lds) {
+        uint32_t N = 64;
+        while (N < n) N <<= 1;
+        for (uint32_t i = tid; i < N; i += RT) L.keys[i] = i < n ? src[i] : ~0ull;
+        __syncthreads();
+        block_sort_lds(L.keys, N, tid);
+    } else {
+        block_sort_global(src, n, L.keys, tid);
     }
-    dim3 g(npix_dev ? PERSIST_LONG : (npix + 3) / 4);
-    switch (cls) {
-        case 1: k_resolve_long<1><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        case 2: k_resolve_long<2><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        case 3: k_resolve_long<4><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        case 4: k_resolve_long<8><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        case 5: k_resolve_long_wide<16><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        case 6: k_resolve_long_wide<32><<<g, 256, 0, s>>>(pix_list, npix, npix_dev, a); break;
-        default: break;
+    const uint64_t *sorted = in_lds ? L.keys : src;
+    const PixelRef pr = pixel_ref(a.tl, p);
+    if (a.sorted_out) {
+        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+        for (uint32_t i = tid; i < n; i += RT) dst[i] = sorted[i];
     }
+    if (a.rgba) {
+        const int lane = tid & 63, wave = tid >> 6;
+        const ShadeParams &sp = a.views[pr.view].sp;
+        const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;  // uniform over the workgroup
+        for (uint32_t r0 = 0; r0 < n; r0 += RT) {
+            const uint32_t e = r0 + tid;
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f, ca = 0.f;
+            if (e < n) {
+                const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(sorted[e] & 0xffffffffu), pr.x, pr.y);
+                c0 = fr.r;
+                c1 = fr.g;
+                c2 = fr.b;
+                ca = fr.a;
+            }
+            over_reduce(c0, c1, c2, ca, lane);
+            if (lane == 0) L.red[wave] = make_float4(c0, c1, c2, ca);
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < RT / 64; ++w) {
+                const float4 q = L.red[w];
+                const float T = 1.f - A;
+                C0 += T * q.x;
+                C1 += T * q.y;
+                C2 += T * q.z;
+                A += T * q.w;
+            }
+            __syncthreads();  // L.red is rewritten by the next round
+            if (1.f - A < T_EPS) break;
+        }
+        if (tid == 0) write_rgba(a, pr, sp, C0, C1, C2, A);
+    }
+    __syncthreads();  // L.keys is reused by the next item
+}
+
+template <int TS>
+struct ResolveLds {
+    union {
+        BlockLds blk;
+        uint64_t col[RT / 64][TS][64];  // short lists: one column per lane
+    };
+};
+
+// The persistent resolve.  Phase 1: lists longer than 256 (classes 7, 6, 5,
+// 4), a workgroup each; phase 2: classes 3, 2, 1, a wave each; phase 3: the
+// short lists (class 0), a lane each, 64 per wave.  List entries equal to
+// PIX_SKIP are skipped.
+// (held to 128 VGPRs: 4 waves per SIMD without spills; at 96 the medium
+// lists' sort and shading spill)
+template <int TS>
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_resolve(ResolveWork w, ResolveArgs a) {
+    __shared__ ResolveLds<TS> L;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t n[NCLASS];
+#pragma unroll
+    for (int c = 0; c < NCLASS; ++c) n[c] = w.n_dev ? (uint32_t)w.n_dev[c] : w.n_host[c];
+    const uint64_t base = (n[0] | n[1] | n[2] | n[3] | n[4] | n[5] | n[6] | n[7]) ? rec_base(a) : 0;
+    // phase 1: a workgroup per list (resolve_block ends on a barrier, after
+    // which L.blk is free for the columns of phase 3)
+    const uint32_t nl = n[7] + n[6] + n[5] + n[4];
+    for (uint32_t it = blockIdx.x; it < nl; it += gridDim.x) {
+        const uint32_t j7 = it, j6 = j7 - n[7], j5 = j6 - n[6], j4 = j5 - n[5];
+        const uint32_t p = it < n[7] ? w.list[7][j7]
+                           : it < n[7] + n[6] ? w.list[6][j6]
+                           : it < n[7] + n[6] + n[5] ? w.list[5][j5] : w.list[4][j4];
+        if (p != PIX_SKIP) resolve_block(a, base, p, L.blk, tid);
+    }
+    // phase 2: a wave per list
+    const uint32_t gw = blockIdx.x * (RT / 64) + wave, nw = gridDim.x * (RT / 64);
+    const uint32_t nm = n[3] + n[2] + n[1];
+    for (uint32_t it = gw; it < nm; it += nw) {
+        if (it < n[3]) {
+            const uint32_t p = w.list[3][it];
+            if (p != PIX_SKIP) resolve_wave<4>(a, base, p, lane);
+        } else if (it < n[3] + n[2]) {
+            const uint32_t p = w.list[2][it - n[3]];
+            if (p != PIX_SKIP) resolve_wave<2>(a, base, p, lane);
+        } else {
+            const uint32_t p = w.list[1][it - n[3] - n[2]];
+            if (p != PIX_SKIP) resolve_wave<1>(a, base, p, lane);
+        }
+    }
+    // phase 3: a lane per list
+    for (uint32_t it = gw; it * 64 < n[0]; it += nw) {
+        const uint32_t idx = it * 64 + lane;
+        if (idx >= n[0]) continue;
+        const uint32_t p = w.list[0][idx];
+        if (p != PIX_SKIP) resolve_lane<TS>(a, base, p, L.col[wave], lane);
+    }
+}
+
+// Persistent grid: as many workgroups as the device holds at once.
+template <int TS>
+static int resident_blocks(int device) {
+    int cus = 0, per = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_resolve<TS>, RT, 0);
+    return std::max(1, cus) * std::max(1, per);
+}
+
+void resolve_grids(int device, int grid[3]) {
+    grid[0] = resident_blocks<16>(device);
+    grid[1] = resident_blocks<32>(device);
+    grid[2] = resident_blocks<64>(device);
+}
+
+void launch_resolve(const ResolveWork &w, int t_sort, const int grid[3], const ResolveArgs &a, hipStream_t s) {
+    const dim3 g((unsigned)grid[t_sort <= 16 ? 0 : t_sort <= 32 ? 1 : 2]);
+    if (t_sort <= 16) k_resolve<16><<<g, RT, 0, s>>>(w, a);
+    else if (t_sort <= 32) k_resolve<32><<<g, RT, 0, s>>>(w, a);
+    else k_resolve<64><<<g, RT, 0, s>>>(w, a);
 }
 
 // ------------------------------------------------------------------ learned tail: head and tail features
@@ -422,20 +621,6 @@ void launch_resolve_class(int cls, const uint32_t *pix_list, uint32_t npix, cons
 // and mean squared depth, the ordered composite of the proxies and the depth
 // where the tail starts.  With TRAIN the tail is also shaded exactly and
 // composited (the regression target).
-__device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, float &A, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o), qa = __shfl_down(A, o);
-        if ((lane & (2 * o - 1)) == 0) {
-            const float T = 1.f - A;
-            C0 += T * q0;
-            C1 += T * q1;
-            C2 += T * q2;
-            A += T * qa;
-        }
-    }
-}
-
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -453,7 +638,7 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     if (wave >= npix) return;
     const uint32_t p = list[wave];
     uint32_t n = min(a.count[p], (uint32_t)(64 * R));
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;
     const uint64_t *src = a.rec + first;
     uint64_t v[R];
@@ -549,19 +734,21 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
 // that sees it is a silhouette pixel when a 4-neighbour inside the image sees
 // none or sees it more than (1 + tau) farther (the depth keys are inverse
 // depths, so the test is key_p > (1 + tau) key_n, in FP64).
-__global__ void __launch_bounds__(256) k_boundary_depth(Tiling tl, int64_t p0, int64_t p1,
+__global__ void __launch_bounds__(256) k_boundary_depth(Tiling tl, const uint64_t *__restrict__ pass_tiles,
                                                         const ViewParams *__restrict__ views,
                                                         const uint32_t *__restrict__ count,
-                                                        const uint64_t *__restrict__ off, int64_t pass_p0,
+                                                        const uint64_t *__restrict__ off,
                                                         const uint64_t *__restrict__ rec, uint64_t rec_cap,
                                                         const uint8_t *__restrict__ face_bnd,
                                                         uint32_t *__restrict__ bdepth) {
+    const int64_t TPX = (int64_t)tl.TW * tl.TH;
+    const int64_t p0 = (int64_t)pass_tiles[0] * TPX, p1 = (int64_t)pass_tiles[1] * TPX;
     const int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= p1) return;
-    const int64_t view = p / ((int64_t)tl.ntiles * tl.TW * tl.TH);
+    const int64_t view = p / ((int64_t)tl.ntiles * TPX);
     if (!(views[view].sp.sil_a > 0.f)) return;
     uint32_t n = count[p];
-    const uint64_t first = off[p] - off[pass_p0];
+    const uint64_t first = off[p] - off[p0];
     if (first + n > rec_cap) n = 0;
     uint64_t best = ~0ull;
     for (uint32_t k = 0; k < n; ++k) {
@@ -607,13 +794,13 @@ __global__ void __launch_bounds__(256) k_silhouette(Tiling tl, int64_t npx, cons
     *o = c;
 }
 
-void launch_boundary_depth(const Tiling &tl, int64_t g0, int64_t g1, const ViewParams *views, const uint32_t *count,
-                           const uint64_t *off, int64_t pass_p0, const uint64_t *rec, uint64_t rec_cap,
+void launch_boundary_depth(const Tiling &tl, int nv, const uint64_t *pass_tiles, const ViewParams *views,
+                           const uint32_t *count, const uint64_t *off, const uint64_t *rec, uint64_t rec_cap,
                            const uint8_t *face_bnd, uint32_t *bdepth, hipStream_t s) {
-    const int64_t TP = (int64_t)tl.TW * tl.TH, p0 = g0 * TP, p1 = g1 * TP;
-    if (p1 <= p0) return;
-    k_boundary_depth<<<dim3((unsigned)((p1 - p0 + 255) / 256)), 256, 0, s>>>(tl, p0, p1, views, count, off, pass_p0,
-                                                                           rec, rec_cap, face_bnd, bdepth);
+    const int64_t n = (int64_t)tl.ntiles * nv * tl.TW * tl.TH;
+    if (n <= 0) return;
+    k_boundary_depth<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(tl, pass_tiles, views, count, off, rec, rec_cap,
+                                                                      face_bnd, bdepth);
 }
 
 void launch_silhouette(const Tiling &tl, int nv, const ViewParams *views, const uint32_t *bdepth, float *rgba,
@@ -686,7 +873,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 template <int R>
 __device__ __forceinline__ uint32_t load_list(const ResolveArgs &a, uint32_t p, int lane, uint64_t (&v)[R]) {
     uint32_t n = min(a.count[p], (uint32_t)(64 * R));
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;
     const uint64_t *src = a.rec + first;
 #pragma unroll
@@ -720,7 +907,7 @@ __global__ void __launch_bounds__(256) k_mlab_shade(const uint32_t *__restrict__
     const PixelRef pr = pixel_ref(a.tl, p);
     const ShadeParams &sp = a.views[pr.view].sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t e = lane * R + r;
@@ -796,7 +983,7 @@ __global__ void __launch_bounds__(256) k_mlab_blend(const uint32_t *__restrict__
     if (i >= npix) return;
     const uint32_t p = list[i];
     uint32_t n = min(a.count[p], nmax);
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;  // (as the shade pass: nothing was stored)
     MlabNodes nd;
     for (uint32_t e = 0; e < n; ++e) nd.insert(mc[first + e], mz[first + e], k);
@@ -816,7 +1003,7 @@ __global__ void __launch_bounds__(64) k_mlab_short(const uint32_t *__restrict__ 
     if (idx >= npix) return;
     const uint32_t p = list[idx];
     uint32_t n = min(a.count[p], (uint32_t)TS);
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;
     const uint64_t *src = a.rec + first;
     for (uint32_t i = 0; i < n; ++i) {
@@ -924,7 +1111,7 @@ __global__ void __launch_bounds__(256) k_moments_short(const uint32_t *__restric
     if (idx >= npix) return;
     const uint32_t p = list[idx];
     uint32_t n = min(a.count[p], (uint32_t)TS);
-    const uint64_t first = a.off[p] - a.off[a.pass_p0];
+    const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;
     const uint64_t *src = a.rec + first;
     const PixelRef pr = pixel_ref(a.tl, p);
