@@ -231,6 +231,8 @@ def main():
         r.render(cams[i % nv], hots[i % nv], styles[i % nv], out=out)
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({nv} sizing + {args.warmup} frames)")
+    for k, st in enumerate(view_stats):
+        log(f"[bench] view {k}: {st['fragments']} fragments, classes {st['classes']}")
     seq = [(args.warmup + i) % nv for i in range(args.steps)]
     frags = sum(view_stats[k]["fragments"] for k in seq)
     bins = sum(view_stats[k]["bins"] for k in seq)

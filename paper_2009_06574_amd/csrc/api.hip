@@ -92,11 +92,15 @@ hexfc_status hexfc_create(int device, hexfc_ctx **out) {
         hipHostMalloc((void **)&ctx->h_stats, sizeof(uint64_t) * ST_COUNT, hipHostMallocDefault) != hipSuccess ||
         ctx->stats.ensure(sizeof(uint64_t) * ST_COUNT) != hipSuccess ||
         ctx->persist.ensure(sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
+        ctx->rqueue.ensure(sizeof(uint32_t) * NCLASS * 8 * QUEUE_STRIDE) != hipSuccess ||
         hipMemset(ctx->persist.p, 0, sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
         hipHostMalloc(&pub, sizeof(uint64_t) * (PS_COUNT + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostGetDevicePointer((void **)&ctx->d_pub, pub, 0) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
         if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
         ctx->h_stats = nullptr;
         if (pub) (void)hipHostFree(pub);
@@ -105,7 +109,7 @@ hexfc_status hexfc_create(int device, hexfc_ctx **out) {
     }
     memset(pub, 0, sizeof(uint64_t) * (PS_COUNT + 1));
     ctx->h_pub = reinterpret_cast<volatile uint64_t *>(pub);
-    resolve_grids(device, ctx->res_grid);
+    resolve_min_grids(device, ctx->res_min_grid);
     if (hipDeviceSynchronize() != hipSuccess) {  // (the counters' zeroing has landed)
         (void)hipHostFree(ctx->h_stats);
         delete ctx;

@@ -77,7 +77,7 @@ struct hexfc_ctx {
     hexfc::DevBuf bdepth;  // per pixel: depth key of the nearest boundary-surface fragment
     hexfc::DevBuf mlab_c, mlab_z;  // per fragment: shaded colour and depth for multi-layer alpha blending
     hexfc::DevBuf vert_b, vscr, fscr, bslot, views, tile_cnt, tile_fill, tile_off, bins, masks, gpre, count, off, scan_tmp, cls,
-        stats, persist;
+        stats, persist, rqueue;
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists
     hexfc::DevBuf l_head, l_feat, l_pix, l_fb;
@@ -89,7 +89,10 @@ struct hexfc_ctx {
     // written by each frame's closing kernel: [0] frames finished, [1 + i] slot i
     volatile uint64_t *h_pub = nullptr;
     uint64_t *d_pub = nullptr;  // its device address
-    int res_grid[3] = {1, 1, 1};  // persistent resolve grids (t_sort <= 16, 32, 64)
+    // the resolve of the longest lists runs on a second stream beside the others
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int res_min_grid[hexfc::NCLASS + 2] = {};  // resident workgroups of each resolve kernel
     // single frames: sizes learned for the current mesh, viewport, tiling and
     // workspace (the first frame of such a combination waits once to learn them)
     bool sized = false;
@@ -126,6 +129,9 @@ struct hexfc_ctx {
         }
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (side_stream) (void)hipStreamDestroy(side_stream);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (h_pub) (void)hipHostFree((void *)h_pub);
     }
 };

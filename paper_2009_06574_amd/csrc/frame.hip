@@ -218,8 +218,8 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, Fron
         launch_plan(tl, ctx->off.as<uint64_t>(), budget, stats, s);
     } else {
         launch_single_pass(nt, stats, s);
-        enqueue_classify(ctx, nv, 0, s);
     }
+    enqueue_classify(ctx, nv, 0, s);  // (the first pass's classes, before any read-back)
 }
 
 // Waits for `s` and copies the device statistics of the last frame to the host.
@@ -304,20 +304,56 @@ ResolveArgs resolve_args(hexfc_ctx *ctx, float *rgba, int pass) {
     return a;
 }
 
-// The class lists of pass k with their sizes in device memory.
-ResolveWork pass_work(hexfc_ctx *ctx, int k) {
-    ResolveWork w;
-    for (int c = 0; c < NCLASS; ++c) {
-        w.list[c] = ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap;
-        w.n_host[c] = 0;
-    }
-    w.n_dev = ctx->stats.as<uint64_t>() + ST_PCLASS + k * NCLASS;
-    return w;
+// The work of one resolve: per length class the list, its size (device or
+// host) and the size the host expects (the grid size).
+struct ResolveSet {
+    ClassWork cls[NCLASS];
+    uint32_t est[NCLASS];
+};
+
+// Class sizes of pass k when the host knows them (the statistics of these
+// lists were read back), else ~0u, and for the short lists (class 0) every
+// pixel of the views (the grid covers a bound of that class).
+void class_estimates(hexfc_ctx *ctx, int k, uint32_t est[NCLASS]) {
+    const bool known = ctx->stats_known && k == 0;
+    for (int c = 0; c < NCLASS; ++c) est[c] = known ? (uint32_t)ctx->last_stats[ST_PCLASS + c] : ~0u;
+    if (!known) est[0] = (uint32_t)std::min<int64_t>((int64_t)ctx->tl.ntiles * ctx->nv * ctx->tl.TW * ctx->tl.TH, 1 << 30);
 }
 
-void enqueue_resolve(hexfc_ctx *ctx, const ResolveWork &w, const ResolveArgs &a, hipStream_t s) {
+// The class lists of pass k with their sizes in device memory.
+ResolveSet pass_set(hexfc_ctx *ctx, int k) {
+    ResolveSet rs;
+    for (int c = 0; c < NCLASS; ++c) {
+        rs.cls[c].list = ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap;
+        rs.cls[c].n_dev = ctx->stats.as<uint64_t>() + ST_PCLASS + k * NCLASS + c;
+        rs.cls[c].n_host = 0;
+        rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
+    }
+    class_estimates(ctx, k, rs.est);
+    return rs;
+}
+
+// One resolve: the classes above 256 fragments (4..7) on the side stream,
+// forked from `s` and joined back, beside classes 3..0 on `s`; longest
+// first on both.  Classes known to be empty are not launched.
+hexfc_status enqueue_resolve(hexfc_ctx *ctx, const ResolveSet &rs, const ResolveArgs &a, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_RESOLVE);
-    launch_resolve(w, ctx->t_sort, ctx->res_grid, a, s);
+    launch_zero_u32(ctx->rqueue.as<uint32_t>(), NCLASS * 8 * QUEUE_STRIDE, s);  // the classes' work queues
+    auto used = [&](int c) { return rs.cls[c].n_dev != nullptr || rs.cls[c].n_host != 0; };
+    const bool side = used(4) || used(5) || used(6) || used(7);
+    if (side) {
+        HIPCHK(ctx, hipEventRecord(ctx->ev_fork, s));
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0));
+        for (int c = NCLASS - 1; c >= 4; --c)
+            if (used(c)) launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, ctx->side_stream);
+    }
+    for (int c = 3; c >= 0; --c)
+        if (used(c)) launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, s);
+    if (side) {
+        HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side_stream));
+        HIPCHK(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
+    }
+    return HEXFC_OK;
 }
 
 void enqueue_fill(hexfc_ctx *ctx, int nv, int k, hipStream_t s) {
@@ -413,7 +449,7 @@ hexfc_status hexfc_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc
     ctx->last_stream = s;
     shade_params(ctx->h_views[0].sp, hot, style);
     TRY(set_views(ctx, 1, s));
-    enqueue_resolve(ctx, pass_work(ctx, 0), resolve_args(ctx, rgba_out, 0), s);
+    TRY(enqueue_resolve(ctx, pass_set(ctx, 0), resolve_args(ctx, rgba_out, 0), s));
     if (style->sil_alpha > 0.f) {
         boundary_depth(ctx, 1, 0, s);
         silhouettes(ctx, 1, rgba_out, s);
@@ -492,7 +528,6 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
             FAIL(ctx, HEXFC_EOVERFLOW, "one screen tile's fragments exceed the workspace (or > %d passes)", MAX_PASSES);
         ctx->passes_launch = (int)std::max<uint64_t>(1, S[ST_NPASS]);
         ctx->sized = true;
-        ctx->stats_known = false;  // (the pass classes are not in last_stats)
     } else {
         if (!cap) TRY(grow_from_published(ctx, ctx->tl));
         TRY(check_views(ctx, 1, cam));
@@ -505,9 +540,9 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
     // planned number find an empty range and return at once
     const bool sil = style->sil_alpha > 0.f;
     for (int k = 0; k < ctx->passes_launch; ++k) {
-        enqueue_classify(ctx, 1, k, s);
+        if (k) enqueue_classify(ctx, 1, k, s);
         enqueue_fill(ctx, 1, k, s);
-        enqueue_resolve(ctx, pass_work(ctx, k), resolve_args(ctx, rgba_out, k), s);
+        TRY(enqueue_resolve(ctx, pass_set(ctx, k), resolve_args(ctx, rgba_out, k), s));
         if (sil) boundary_depth(ctx, 1, k, s);
     }
     if (sil) silhouettes(ctx, 1, rgba_out, s);
@@ -572,7 +607,8 @@ hexfc_status hexfc_render_batch(hexfc_ctx *ctx, int n, const hexfc_camera *cams,
     if (e == hipSuccess) {
         enqueue_front(ctx, n, ctx->tl, cs, FRONT_SINGLE);
         enqueue_fill(ctx, n, 0, cs);
-        enqueue_resolve(ctx, pass_work(ctx, 0), resolve_args(ctx, rgba_out, 0), cs);
+        if (e == hipSuccess && enqueue_resolve(ctx, pass_set(ctx, 0), resolve_args(ctx, rgba_out, 0), cs) != HEXFC_OK)
+            e = hipErrorUnknown;
         // silhouettes (the kernels skip the views whose sil_alpha is 0)
         boundary_depth(ctx, n, 0, cs);
         silhouettes(ctx, n, rgba_out, cs);
@@ -648,7 +684,7 @@ hexfc_status hexfc_export_sorted_lists(hexfc_ctx *ctx, uint32_t *counts_out, uin
     ResolveArgs a = resolve_args(ctx, nullptr, 0);
     a.sorted_out = rec_out;
     a.off_rm = off_out;
-    enqueue_resolve(ctx, pass_work(ctx, 0), a, s);
+    TRY(enqueue_resolve(ctx, pass_set(ctx, 0), a, s));
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }
@@ -739,10 +775,11 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
     if (mask_out) launch_fill_u8(mask_out, (int64_t)tl.W * tl.H, 1, s);
     launch_zero_u64(stats + ST_FB, NCLASS, s);
     if (ctx->last_stats[ST_CLASS]) {  // short lists: exact
-        ResolveWork w{};
-        w.list[0] = ctx->cls.as<uint32_t>();
-        w.n_host[0] = (uint32_t)ctx->last_stats[ST_CLASS];
-        enqueue_resolve(ctx, w, a, s);
+        ResolveSet rs{};
+        rs.cls[0].list = ctx->cls.as<uint32_t>();
+        rs.cls[0].queue = ctx->rqueue.as<uint32_t>();
+        rs.est[0] = rs.cls[0].n_host = (uint32_t)ctx->last_stats[ST_CLASS];
+        TRY(enqueue_resolve(ctx, rs, a, s));
     }
     if (rows) {
         float *head = ctx->l_head.as<float>(), *feat = ctx->l_feat.as<float>();
@@ -754,14 +791,19 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
         }
         // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
         ScopedTimer tm(ctx, s, KID_FALLBACK);
-        ResolveWork w{};
+        ResolveSet rs{};
         int64_t base = 0;
         for (int c = 1; c < NCLASS - 1; ++c) {
-            w.list[c] = fb + base;
-            w.n_host[c] = (uint32_t)ctx->last_stats[ST_CLASS + c];
-            base += w.n_host[c];
+            rs.cls[c].list = fb + base;
+            rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
+            rs.est[c] = rs.cls[c].n_host = (uint32_t)ctx->last_stats[ST_CLASS + c];
+            base += rs.cls[c].n_host;
         }
-        launch_resolve(w, ctx->t_sort, ctx->res_grid, a, s);
+        const bool prof = ctx->prof;
+        ctx->prof = false;  // (timed as the fallback)
+        const hexfc_status st = enqueue_resolve(ctx, rs, a, s);
+        ctx->prof = prof;
+        TRY(st);
     }
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;

@@ -786,6 +786,12 @@ __global__ void k_finish(uint64_t *__restrict__ stats, uint64_t *__restrict__ pe
     persist[PS_FLAGGED] += flags ? 1 : 0;
     persist[PS_LAST_FLAGS] = flags;
     persist[PS_LAST_FRAGS] = stats[ST_FRAGS];
+    const uint64_t np = min(stats[ST_NPASS], (uint64_t)MAX_PASSES);
+    for (int c = 0; c < NCLASS; ++c) {
+        uint64_t m = 0;
+        for (uint64_t k = 0; k < np; ++k) m = max(m, stats[ST_PCLASS + k * NCLASS + c]);
+        persist[PS_CLASS + c] = m;
+    }
     if (published) {
         for (int i = 0; i < PS_COUNT; ++i) published[1 + i] = persist[i];
         __threadfence_system();

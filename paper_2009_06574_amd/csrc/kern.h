@@ -55,7 +55,9 @@ enum FrameFlag {
 // without waiting on any of them; copied after every frame into host-mapped
 // memory by the closing kernel
 enum PersistSlot {
-    PS_MAX_BINS = 0, PS_MAX_PASSES, PS_FRAMES, PS_FLAGGED, PS_LAST_FLAGS, PS_LAST_FRAGS, PS_COUNT = 8
+    PS_MAX_BINS = 0, PS_MAX_PASSES, PS_FRAMES, PS_FLAGGED, PS_LAST_FLAGS, PS_LAST_FRAGS,
+    PS_CLASS = 8,   // NCLASS: per class, the largest size over the passes of the last frame
+    PS_COUNT = 16
 };
 
 // kernels timed by the optional per-launch HIP-event profiler
@@ -233,19 +235,25 @@ struct ResolveArgs {
     uint64_t *sorted_out;     // nullable: sorted records, row-major CSR (single view)
     const uint64_t *off_rm;   // row-major offsets for sorted_out
 };
-// The pixels one resolve launch handles: per length class a list of global
+// The pixels of one length class for a resolve launch: a list of global
 // pixel ids (entries equal to PIX_SKIP are skipped) and its size, from device
-// memory (n_dev, NCLASS values) or, when n_dev is null, from n_host.
+// memory (n_dev) or, when n_dev is null, n_host.
 constexpr uint32_t PIX_SKIP = 0xffffffffu;
-struct ResolveWork {
-    const uint32_t *list[NCLASS];
+struct ClassWork {
+    const uint32_t *list;
     const uint64_t *n_dev;
-    uint32_t n_host[NCLASS];
+    uint32_t n_host;
+    uint32_t *queue;  // 8 * QUEUE_STRIDE u32 of work-queue counters, zero at launch
 };
-// Persistent grid sizes of the resolve for t_sort <= 16, <= 32, <= 64
-// (workgroups the device holds at once).
-void resolve_grids(int device, int grid[3]);
-void launch_resolve(const ResolveWork &w, int t_sort, const int grid[3], const ResolveArgs &a, hipStream_t s);
+constexpr int QUEUE_STRIDE = 32;  // one counter per 128-byte line
+// Resolve of class c (see NCLASS).  est: the class size when the host knows
+// it (a smaller grid for a short list), else ~0u (a resident grid); the
+// kernel takes the true size from device memory either way.
+// min_grid: resolve_min_grids(), the workgroups of each class kernel the
+// device holds at once (classes 0..7, then class 0 for t_sort <= 32, <= 64).
+void resolve_min_grids(int device, int min_grid[NCLASS + 2]);
+void launch_resolve_class(int c, const ClassWork &w, uint32_t est, int t_sort, const int min_grid[NCLASS + 2],
+                          const ResolveArgs &a, hipStream_t s);
 
 // Learned tail (resolve.hip): for the pixels of long-list class cls, the exact
 // composite of the first K sorted fragments (head[4]), 9 tail features and,

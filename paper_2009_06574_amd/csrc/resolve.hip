@@ -44,19 +44,20 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
     const bool t1 = tri & 1;
     const FaceRec F = m.face[f];
     const int4 c = F.c;
-    const VertRec V0 = vert[c.x], V1 = vert[c.y], V2 = vert[c.z], V3 = vert[c.w];
-    const int4 s0 = V0.scr, s1 = t1 ? V2.scr : V1.scr, s2 = t1 ? V3.scr : V2.scr;
+    // the triangle's screen vertices: corners 0, 1 + t, 2 + t
+    const int4 s0 = vert[c.x].scr, s1 = vert[t1 ? c.z : c.y].scr, s2 = vert[t1 ? c.w : c.z].scr;
     // perspective-correct barycentrics: weight of vertex i = E_opp(i) * q_i,
-    // the edge functions being exact in FP64
-    const double X = (double)(SUB * x + SUB / 2), Y = (double)(SUB * y + SUB / 2);
-    const double e0 = (double)(s2.x - s1.x) * (Y - s1.y) - (double)(s2.y - s1.y) * (X - s1.x);
-    const double e1 = (double)(s0.x - s2.x) * (Y - s2.y) - (double)(s0.y - s2.y) * (X - s2.x);
-    const double e2 = (double)(s1.x - s0.x) * (Y - s0.y) - (double)(s1.y - s0.y) * (X - s0.x);
-    const double w0 = e0 * (double)s0.z, w1 = e1 * (double)s1.z, w2 = e2 * (double)s2.z;
-    const float inv = __builtin_amdgcn_rcpf((float)(w0 + w1 + w2));
-    const float l0 = (float)w0 * inv, l1 = (float)w1 * inv, l2 = (float)w2 * inv;
+    // the edge functions exact in integers (each factor below 2^18), the
+    // weights in FP32 (positive inside the triangle: no cancellation)
+    const int X = SUB * x + SUB / 2, Y = SUB * y + SUB / 2;
+    const long long e0 = (long long)(s2.x - s1.x) * (Y - s1.y) - (long long)(s2.y - s1.y) * (X - s1.x);
+    const long long e1 = (long long)(s0.x - s2.x) * (Y - s2.y) - (long long)(s0.y - s2.y) * (X - s2.x);
+    const long long e2 = (long long)(s1.x - s0.x) * (Y - s0.y) - (long long)(s1.y - s0.y) * (X - s0.x);
+    const float w0 = (float)e0 * (float)s0.z, w1 = (float)e1 * (float)s1.z, w2 = (float)e2 * (float)s2.z;
+    const float inv = __builtin_amdgcn_rcpf(w0 + w1 + w2);
+    const float l0 = w0 * inv, l1 = w1 * inv, l2 = w2 * inv;
     // corners relative to corner 0 (exact: all are multiples of 2^-16)
-    const float4 P0 = V0.world, P1 = V1.world, P2 = V2.world, P3 = V3.world;
+    const float4 P0 = vert[c.x].world, P1 = vert[c.y].world, P2 = vert[c.z].world, P3 = vert[c.w].world;
     const float r1x = P1.x - P0.x, r1y = P1.y - P0.y, r1z = P1.z - P0.z;
     const float r2x = P2.x - P0.x, r2y = P2.y - P0.y, r2z = P2.z - P0.z;
     const float r3x = P3.x - P0.x, r3y = P3.y - P0.y, r3z = P3.z - P0.z;
@@ -137,15 +138,17 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
 
 constexpr float T_EPS = 9.5367431640625e-07f;  // 2^-20: stop once 1 - A is below it
 
-// ------------------------------------------------------------------ one persistent resolve
-// Every pixel of a pass is resolved by one persistent launch that takes the
-// lists longest first: the length classes are walked from the longest (a
-// workgroup per pixel) through the medium ones (a wave per pixel) to the
-// short ones (a lane per pixel), and within each phase the items are dealt
-// to the workgroups (or waves) round-robin, so the few very long lists start
-// at once and the many short ones fill in behind them.  The class lists and
-// their sizes come from device memory: nothing about the frame's lists is
-// known to the host when the launch is enqueued.
+// ------------------------------------------------------------------ resolve by length class
+// The pixels of a pass are resolved by one kernel per length class, each
+// specialised for its lists: a lane per pixel (insertion sort in LDS) for the
+// short lists, a wave per pixel (bitonic sort in registers) up to 2048
+// fragments, a workgroup per pixel (sorted in place) beyond.  Every kernel
+// strides over its class list, whose size it reads from device memory, so
+// its grid needs no exact count: the host sizes it from the counts it knows
+// (exact after a statistics read-back, else those of the last finished
+// frame).  The classes above 256 fragments run on a second stream next to
+// the others, longest first on both, so that the few long lists do not form
+// a tail of their own (see the frame orchestration).
 
 constexpr int RT = 256;      // threads of the resolve workgroup (4 waves)
 constexpr int LCAP = 2048;   // longest list a workgroup sorts in LDS; longer ones are sorted in place
@@ -297,86 +300,113 @@ __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRe
     return true;
 }
 
-// Medium list of pixel p (n <= 64 R): one wave, bitonic sort in registers.
+// Wavefront-scope ordering of a wave's LDS stash accesses (stores by some
+// lanes, loads by others) without a workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// List of pixel p (n <= 64 R): one wave, bitonic sort in registers.  Up to
+// 256 elements (R <= 4) the sorted keys go to `stash` (2 KB of LDS private to
+// the wave) for the shading rounds, so that they hold no registers across
+// the shading; longer lists keep them in registers.
 template <int R>
-__device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint64_t base, uint32_t p, int lane) {
+__device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint64_t base, uint32_t p, int lane,
+                                             uint32_t *__restrict__ stash) {
     uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
     const uint64_t first = a.off[p] - base;
     if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
     const uint64_t *src = a.rec + first;
     const PixelRef pr = pixel_ref(a.tl, p);
-    // Rendering only (no sorted export): sort 32-bit keys (depth << 8 |
-    // position in the list; depths stay below 2^24 - 1, so the padding ~0
-    // sorts last) and keep the triangle ids where they were loaded.  Equal
-    // depths must be ordered by triangle id, which these keys do not hold: the
-    // rounds stop short of the first such pair, and a pixel that needs
-    // fragments past it takes the 64-bit sort below.
-    if (!a.sorted_out) {
-        if (!a.rgba) return;
-        uint32_t key[R], tri[R];
+    if constexpr (R <= 4) {
+        // Rendering only (no sorted export): sort 32-bit keys (depth << 8 |
+        // position in the list; depths stay below 2^24 - 1, so the padding ~0
+        // sorts last); the triangle ids stay in the stash at their list
+        // positions.  Equal depths must be ordered by triangle id, which these
+        // keys do not hold: the rounds stop short of the first such pair, and a
+        // pixel that needs fragments past it takes the 64-bit sort below.
+        uint32_t *skey = stash, *stri = stash + 256;
+        if (!a.sorted_out) {
+            if (!a.rgba) return;
+            uint32_t key[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e = lane * R + r;
+                const uint64_t rec = e < n ? src[e] : ~0ull;
+                key[r] = e < n ? ((uint32_t)(rec >> 32) << 8) | e : ~0u;
+                stri[e] = (uint32_t)rec;
+            }
+            bitonic_sort<R>(key, lane);
+            // first position e with equal depths at e and e + 1
+            const uint32_t nxt = __shfl_down(key[0], 1);
+            uint32_t tie = ~0u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
+                const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
+                const uint64_t b = __ballot(t);
+                if (b) tie = min(tie, (uint32_t)__builtin_ctzll(b) * R + r);
+                skey[lane * R + r] = key[r];
+            }
+            wave_lds_sync();
+            const bool done = shade_rounds<R>(a, pr, n, lane, tie,
+                                              [&](int k) { return stri[skey[64u * k + lane] & 0xffu]; });
+            wave_lds_sync();  // (the stash is rewritten next)
+            if (done) return;
+        }
+        uint64_t v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t e = lane * R + r;
-            const uint64_t rec = e < n ? src[e] : ~0ull;
-            key[r] = e < n ? ((uint32_t)(rec >> 32) << 8) | e : ~0u;
-            tri[r] = (uint32_t)rec;
+            v[r] = e < n ? src[e] : ~0ull;
         }
-        bitonic_sort<R>(key, lane);
-        // first position e with equal depths at e and e + 1
-        const uint32_t nxt = __shfl_down(key[0], 1);
-        uint32_t tie = ~0u;
+        bitonic_sort<R>(v, lane);
+        if (a.sorted_out) {
+            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
-            const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
-            const uint64_t b = __ballot(t);
-            if (b) tie = min(tie, (uint32_t)__builtin_ctzll(b) * R + r);
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e = lane * R + r;
+                if (e < n) dst[e] = v[r];
+            }
         }
-        const bool done = shade_rounds<R>(a, pr, n, lane, tie, [&](int k) {
-            const uint32_t e = 64u * k + lane;
-            uint32_t sk = ~0u;
+        if (a.rgba) {
+            // the sorted triangle ids to the stash, element e at position e
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const uint32_t t = __shfl(key[rr], (int)(e / R));
-                if ((int)(e % R) == rr) sk = t;
-            }
-            const uint32_t idx = sk & 0xffu;
-            uint32_t tr = 0;
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const uint32_t t = __shfl(tri[rr], (int)(idx / R));
-                if ((int)(idx % R) == rr) tr = t;
-            }
-            return tr;
-        });
-        if (done) return;
-    }
-    uint64_t v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t e = lane * R + r;
-        v[r] = e < n ? src[e] : ~0ull;
-    }
-    bitonic_sort<R>(v, lane);
-    if (a.sorted_out) {
-        uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
+            for (int r = 0; r < R; ++r) stri[lane * R + r] = (uint32_t)v[r];
+            wave_lds_sync();
+            shade_rounds<R>(a, pr, n, lane, ~0u, [&](int k) { return stri[64u * k + lane]; });
+            wave_lds_sync();  // (the stash is rewritten by the wave's next list)
+        }
+    } else {
+        uint64_t v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t e = lane * R + r;
-            if (e < n) dst[e] = v[r];
+            v[r] = e < n ? src[e] : ~0ull;
         }
-    }
-    if (a.rgba)
-        shade_rounds<R>(a, pr, n, lane, ~0u, [&](int k) {
-            const uint32_t e = 64u * k + lane;
-            uint64_t x = ~0ull;
+        bitonic_sort<R>(v, lane);
+        if (a.sorted_out) {
+            uint64_t *dst = a.sorted_out + a.off_rm[(int64_t)pr.y * a.tl.W + pr.x];
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const uint64_t t = __shfl(v[rr], (int)(e / R));
-                if ((int)(e % R) == rr) x = t;
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e = lane * R + r;
+                if (e < n) dst[e] = v[r];
             }
-            return (uint32_t)(x & 0xffffffffu);
-        });
+        }
+        if (a.rgba)
+            shade_rounds<R>(a, pr, n, lane, ~0u, [&](int k) {
+                const uint32_t e = 64u * k + lane;
+                uint64_t x = ~0ull;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const uint64_t t = __shfl(v[rr], (int)(e / R));
+                    if ((int)(e % R) == rr) x = t;
+                }
+                return (uint32_t)(x & 0xffffffffu);
+            });
+    }
 }
 
 // Ascending compare-exchange of two 64-bit keys at lo < hi.
@@ -473,9 +503,9 @@ struct BlockLds {
     float4 red[RT / 64];
 };
 
-// Long list of pixel p (n > 256): one workgroup sorts it (in LDS when it
-// fits, else in place) and shades it in rounds of 256 fragments, the four
-// waves' ordered composites being combined in wave order.
+// Very long list of pixel p (n > 2048): one workgroup sorts it in place and
+// shades it in rounds of 256 fragments, the four waves' ordered composites
+// being combined in wave order.
 __device__ void resolve_block(const ResolveArgs &a, uint64_t base, uint32_t p, BlockLds &L, int tid) {
     uint32_t n = a.count[p];
     const uint64_t first = a.off[p] - base;
@@ -532,83 +562,151 @@ __device__ void resolve_block(const ResolveArgs &a, uint64_t base, uint32_t p, B
     __syncthreads();  // L.keys is reused by the next item
 }
 
-template <int TS>
-struct ResolveLds {
-    union {
-        BlockLds blk;
-        uint64_t col[RT / 64][TS][64];  // short lists: one column per lane
-    };
-};
+__device__ __forceinline__ uint32_t class_size(const ClassWork &w) {
+    return w.n_dev ? (uint32_t)*w.n_dev : w.n_host;
+}
 
-// The persistent resolve.  Phase 1: lists longer than 256 (classes 7, 6, 5,
-// 4), a workgroup each; phase 2: classes 3, 2, 1, a wave each; phase 3: the
-// short lists (class 0), a lane each, 64 per wave.  List entries equal to
-// PIX_SKIP are skipped.
-// (held to 128 VGPRs: 4 waves per SIMD without spills; at 96 the medium
-// lists' sort and shading spill)
-template <int TS>
-__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_resolve(ResolveWork w, ResolveArgs a) {
-    __shared__ ResolveLds<TS> L;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t n[NCLASS];
-#pragma unroll
-    for (int c = 0; c < NCLASS; ++c) n[c] = w.n_dev ? (uint32_t)w.n_dev[c] : w.n_host[c];
-    const uint64_t base = (n[0] | n[1] | n[2] | n[3] | n[4] | n[5] | n[6] | n[7]) ? rec_base(a) : 0;
-    // phase 1: a workgroup per list (resolve_block ends on a barrier, after
-    // which L.blk is free for the columns of phase 3)
-    const uint32_t nl = n[7] + n[6] + n[5] + n[4];
-    for (uint32_t it = blockIdx.x; it < nl; it += gridDim.x) {
-        const uint32_t j7 = it, j6 = j7 - n[7], j5 = j6 - n[6], j4 = j5 - n[5];
-        const uint32_t p = it < n[7] ? w.list[7][j7]
-                           : it < n[7] + n[6] ? w.list[6][j6]
-                           : it < n[7] + n[6] + n[5] ? w.list[5][j5] : w.list[4][j4];
-        if (p != PIX_SKIP) resolve_block(a, base, p, L.blk, tid);
-    }
-    // phase 2: a wave per list
-    const uint32_t gw = blockIdx.x * (RT / 64) + wave, nw = gridDim.x * (RT / 64);
-    const uint32_t nm = n[3] + n[2] + n[1];
-    for (uint32_t it = gw; it < nm; it += nw) {
-        if (it < n[3]) {
-            const uint32_t p = w.list[3][it];
-            if (p != PIX_SKIP) resolve_wave<4>(a, base, p, lane);
-        } else if (it < n[3] + n[2]) {
-            const uint32_t p = w.list[2][it - n[3]];
-            if (p != PIX_SKIP) resolve_wave<2>(a, base, p, lane);
-        } else {
-            const uint32_t p = w.list[1][it - n[3] - n[2]];
-            if (p != PIX_SKIP) resolve_wave<1>(a, base, p, lane);
+// Dynamic distribution of a class list over the resident waves (what a grid
+// of one workgroup per list item would get from the hardware dispatcher,
+// without knowing the list's size when the grid is launched).  The list is
+// cut into 8 contiguous segments, one per XCD (workgroups are dealt to the
+// XCDs round-robin, and an XCD's waves share an L2 in which neighbouring
+// pixels find the faces they shade); a wave pops the next item of its XCD's
+// segment, with the next pop in flight while it works on the current one,
+// then helps with what is left of the other segments.  `body(item)` is
+// called by the whole wave with a wave-uniform item.
+template <int PER_POP, class Body>
+__device__ __forceinline__ void drain(uint32_t total, uint32_t *__restrict__ queue, int lane, Body &&body) {
+    const int xcd = blockIdx.x & 7;
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int x = (xcd + h) & 7;
+        const uint32_t lo = (uint32_t)((uint64_t)total * x / 8), hi = (uint32_t)((uint64_t)total * (x + 1) / 8);
+        uint32_t *ctr = queue + x * QUEUE_STRIDE;
+        if (lo == hi || (h && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo))
+            continue;  // (an empty segment, or one already taken)
+        uint32_t got = 0;
+        if (lane == 0) got = atomicAdd(ctr, (uint32_t)PER_POP);
+        uint32_t it = lo + __builtin_amdgcn_readfirstlane(got);
+        while (it < hi) {
+            uint32_t next = 0;
+            if (lane == 0) next = atomicAdd(ctr, (uint32_t)PER_POP);  // (in flight during the items below)
+#pragma unroll 1
+            for (uint32_t j = it; j < min(it + PER_POP, hi); ++j) body(j);
+            it = lo + __builtin_amdgcn_readfirstlane(next);
         }
-    }
-    // phase 3: a lane per list
-    for (uint32_t it = gw; it * 64 < n[0]; it += nw) {
-        const uint32_t idx = it * 64 + lane;
-        if (idx >= n[0]) continue;
-        const uint32_t p = w.list[0][idx];
-        if (p != PIX_SKIP) resolve_lane<TS>(a, base, p, L.col[wave], lane);
     }
 }
 
-// Persistent grid: as many workgroups as the device holds at once.
+// Short lists (class 0): a lane per pixel, 64 pixels per workgroup; the grid
+// covers a bound of the class size (most pixels are short: few workgroups
+// find nothing to do), dealt to the XCDs in contiguous ranges of the true
+// size, each workgroup a chunk as the hardware dispatches it.
 template <int TS>
-static int resident_blocks(int device) {
+__global__ void __launch_bounds__(64) k_resolve_short(ClassWork w, ResolveArgs a) {
+    __shared__ uint64_t col[TS][64];
+    const int lane = threadIdx.x;
+    const uint32_t total = class_size(w);
+    const uint32_t chunks = (total + 63) / 64;
+    if (blockIdx.x >= chunks && gridDim.x >= chunks) return;
+    const uint64_t base = rec_base(a);
+    // (a grid smaller than the list strides over it)
+    for (uint32_t b = blockIdx.x; b < chunks; b += gridDim.x) {
+        const uint32_t chunk = gridDim.x >= chunks ? xcd_contiguous(b, chunks) : b;
+        const uint32_t idx = chunk * 64 + lane;
+        if (idx >= total) continue;
+        const uint32_t p = w.list[idx];
+        if (p != PIX_SKIP) resolve_lane<TS>(a, base, p, col, lane);
+    }
+}
+
+// Wave-per-pixel lists (classes 1..6).  Up to 8 keys per lane the kernel is
+// held to 96 VGPRs (5 waves per SIMD).
+template <int R>
+__device__ __forceinline__ void resolve_waves(const ClassWork &w, const ResolveArgs &a) {
+    __shared__ uint32_t stash[RT / 64][R <= 4 ? 512 : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t total = class_size(w);
+    if (!total) return;
+    const uint64_t base = rec_base(a);
+    // (short lists take several items per pop: their work would not hide its latency)
+    drain<R == 1 ? 4 : R == 2 ? 2 : 1>(total, w.queue, lane, [&](uint32_t item) {
+        const uint32_t p = w.list[item];
+        if (p != PIX_SKIP) resolve_wave<R>(a, base, p, lane, stash[wave]);
+    });
+}
+template <int R>
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(5, 8))) k_resolve_wave(ClassWork w,
+                                                                                              ResolveArgs a) {
+    resolve_waves<R>(w, a);
+}
+template <int R>
+__global__ void __launch_bounds__(RT) k_resolve_wave_wide(ClassWork w, ResolveArgs a) {
+    resolve_waves<R>(w, a);
+}
+
+// Lists longer than 2048 (class 7): a workgroup per pixel (few of them:
+// dealt round-robin to the workgroups).
+__global__ void __launch_bounds__(RT) k_resolve_block(ClassWork w, ResolveArgs a) {
+    __shared__ BlockLds L;
+    const uint32_t total = class_size(w);
+    if (!total) return;
+    const uint64_t base = rec_base(a);
+    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t p = w.list[it];
+        if (p != PIX_SKIP) resolve_block(a, base, p, L, threadIdx.x);
+    }
+}
+
+// Workgroups of each class kernel the device holds at once (the grid is never
+// smaller: a low estimate then costs the balance of a persistent grid, not
+// a few workgroups striding over a long list).
+template <class K>
+static int resident(int device, K kernel, int threads) {
     int cus = 0, per = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_resolve<TS>, RT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
     return std::max(1, cus) * std::max(1, per);
 }
 
-void resolve_grids(int device, int grid[3]) {
-    grid[0] = resident_blocks<16>(device);
-    grid[1] = resident_blocks<32>(device);
-    grid[2] = resident_blocks<64>(device);
+void resolve_min_grids(int device, int out[NCLASS + 2]) {
+    out[0] = resident(device, k_resolve_short<16>, 64);
+    out[1] = resident(device, k_resolve_wave<1>, RT);
+    out[2] = resident(device, k_resolve_wave<2>, RT);
+    out[3] = resident(device, k_resolve_wave<4>, RT);
+    out[4] = resident(device, k_resolve_wave<8>, RT);
+    out[5] = resident(device, k_resolve_wave_wide<16>, RT);
+    out[6] = resident(device, k_resolve_wave_wide<32>, RT);
+    out[7] = resident(device, k_resolve_block, RT);
+    out[8] = resident(device, k_resolve_short<32>, 64);
+    out[9] = resident(device, k_resolve_short<64>, 64);
 }
 
-void launch_resolve(const ResolveWork &w, int t_sort, const int grid[3], const ResolveArgs &a, hipStream_t s) {
-    const dim3 g((unsigned)grid[t_sort <= 16 ? 0 : t_sort <= 32 ? 1 : 2]);
-    if (t_sort <= 16) k_resolve<16><<<g, RT, 0, s>>>(w, a);
-    else if (t_sort <= 32) k_resolve<32><<<g, RT, 0, s>>>(w, a);
-    else k_resolve<64><<<g, RT, 0, s>>>(w, a);
+void launch_resolve_class(int c, const ClassWork &w, uint32_t est, int t_sort, const int min_grid[NCLASS + 2],
+                          const ResolveArgs &a, hipStream_t s) {
+    // class 0: a workgroup per 64 pixels of est (here a bound of the class
+    // size); classes 1..6 drain their lists dynamically on a resident grid,
+    // smaller when the list is known to be short; class 7: a workgroup per list
+    const unsigned per = c == 0 ? 64u : c == 7 ? 1u : 4u;  // pixels per workgroup
+    const unsigned res = (unsigned)(c == 0 ? min_grid[t_sort <= 16 ? 0 : t_sort <= 32 ? 8 : 9] : min_grid[c]);
+    const unsigned need = est == ~0u ? res : (est + per - 1) / per;
+    const dim3 g(std::max(1u, c == 0   ? std::min(std::max(need, res), 1u << 22)
+                              : c == 7 ? std::min(std::max(need, 64u), res)
+                                       : std::min(need + 64u, res)));
+    switch (c) {
+        case 0:
+            if (t_sort <= 16) k_resolve_short<16><<<g, 64, 0, s>>>(w, a);
+            else if (t_sort <= 32) k_resolve_short<32><<<g, 64, 0, s>>>(w, a);
+            else k_resolve_short<64><<<g, 64, 0, s>>>(w, a);
+            break;
+        case 1: k_resolve_wave<1><<<g, RT, 0, s>>>(w, a); break;
+        case 2: k_resolve_wave<2><<<g, RT, 0, s>>>(w, a); break;
+        case 3: k_resolve_wave<4><<<g, RT, 0, s>>>(w, a); break;
+        case 4: k_resolve_wave<8><<<g, RT, 0, s>>>(w, a); break;
+        case 5: k_resolve_wave_wide<16><<<g, RT, 0, s>>>(w, a); break;
+        case 6: k_resolve_wave_wide<32><<<g, RT, 0, s>>>(w, a); break;
+        default: k_resolve_block<<<g, RT, 0, s>>>(w, a); break;
+    }
 }
 
 // ------------------------------------------------------------------ learned tail: head and tail features
