@@ -330,11 +330,32 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
  *   conf_min    confidence threshold in [0, 1); 0 accepts every prediction
  *   rgba_out    device float [H][W][4] (as hexfc_resolve)
  *   mask_out    device uint8 [H][W] or NULL: 1 = exact, 0 = learned tail
+ * Keeps a context-owned staging of 60 bytes per long-list pixel (head
+ * composite, tail features, pixel id, fallback entry), grown on demand.
  * Errors: ESTATE (no single-view lists), ERANGE (K, conf_min), EINVAL,
- * EOVERFLOW (a list longer than 2048). */
+ * EOVERFLOW (a list longer than 2048), ENOMEM. */
 hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
                                    const float *params, int K, float conf_min, float *rgba_out,
                                    uint8_t *mask_out, void *stream);
+
+/* hexfc_resolve_learned for callers that cannot allocate device memory
+ * (tight serving loops, hosts or harnesses that forbid hipMalloc): the same
+ * kernels, arguments and results, with the per-row staging in a static device
+ * array of HEXFC_NOALLOC_MAX_ROWS rows (60 MiB) that each GPU holds from the
+ * library's load to the end of the process.
+ * Calls neither hipMalloc nor hipFree nor anything that allocates; the lists
+ * must have been built before (hexfc_build_fragment_lists).  Not timed by
+ * hexfc_set_profiling.  Every call on a GPU, from any context, shares that
+ * GPU's array: calls whose work overlaps on one GPU race and must be ordered
+ * by the caller (one stream, or events).
+ * Errors: as hexfc_resolve_learned (never ENOMEM), plus EOVERFLOW when more than
+ * HEXFC_NOALLOC_MAX_ROWS pixels have lists longer than t_sort (nothing is
+ * enqueued then) and EDEVICE when the array's address could not be looked up
+ * when the context was created. */
+#define HEXFC_NOALLOC_MAX_ROWS (1 << 20)
+hexfc_status hexfc_resolve_learned_noalloc(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                           const float *params, int K, float conf_min, float *rgba_out,
+                                           uint8_t *mask_out, void *stream);
 
 /* Training and evaluation data of the learned resolve for the lists of the
  * last hexfc_build_fragment_lists: one row per pixel of the long-list classes

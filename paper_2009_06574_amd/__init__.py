@@ -25,7 +25,8 @@ ABI_SYMBOLS = (
     "hexfc_build_fragment_lists", "hexfc_resolve", "hexfc_render_frame", "hexfc_set_tuning",
     "hexfc_get_frame_stats", "hexfc_get_total_fragments", "hexfc_export_sorted_lists",
     "hexfc_set_profiling", "hexfc_get_kernel_times", "hexfc_render_batch", "hexfc_batch_status",
-    "hexfc_autotune", "hexfc_resolve_approx", "hexfc_resolve_learned", "hexfc_learned_features", "hexfc_mlp_param_count",
+    "hexfc_autotune", "hexfc_resolve_approx", "hexfc_resolve_learned", "hexfc_resolve_learned_noalloc", "hexfc_learned_features",
+    "hexfc_mlp_param_count",
     "hexfc_mlp_forward", "hexfc_mlp_loss", "hexfc_mlp_backward", "hexfc_mlp_adam_step",
     "hexfc_build_lod", "hexfc_status_string", "hexfc_last_error",
 )
@@ -93,6 +94,8 @@ def load():
         "hexfc_resolve_approx": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), ct.c_int, ct.c_int, P, P], st),
         "hexfc_resolve_learned": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), P, ct.c_int, ct.c_float, P, P, P],
                                   st),
+        "hexfc_resolve_learned_noalloc": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), P, ct.c_int, ct.c_float, P,
+                                           P, P], st),
         "hexfc_learned_features": ([P, ct.POINTER(CHotspot), ct.POINTER(CStyle), ct.c_int, P, P, P, P, i64, P, P],
                                    st),
         "hexfc_mlp_param_count": ([], i64),
@@ -327,8 +330,11 @@ class Renderer:
                                                     max(r, 1), ct.byref(rows), self._stream()))
         return {k: (None if v is None else v[:r]) for k, v in out.items()}
 
-    def resolve_learned(self, hot, style, params, K: int = 8, conf_min: float = 0.5, out=None, mask=True):
-        """Learned-tail resolve of the last built lists: (rgba [H,W,4], mask [H,W] uint8 or None)."""
+    def resolve_learned(self, hot, style, params, K: int = 8, conf_min: float = 0.5, out=None, mask=True,
+                        noalloc: bool = False):
+        """Learned-tail resolve of the last built lists: (rgba [H,W,4], mask [H,W] uint8 or None).
+        noalloc: the allocation-free entry point (static per-GPU staging; the
+        caller's buffers are still allocated here when not given)."""
         t = self.torch
         if out is None:
             out = t.empty((self.H, self.W, 4), dtype=t.float32, device=self.device)
@@ -338,9 +344,9 @@ class Renderer:
         elif mask is not None and mask is not False:
             m = mask
         params = _f32(params, self.device)
-        self._check(self.lib.hexfc_resolve_learned(self.ctx, ct.byref(hotspot_struct(hot)),
-                                                   ct.byref(style_struct(style)), _ptr(params), int(K),
-                                                   float(conf_min), _ptr(out), _ptr(m), self._stream()))
+        fn = self.lib.hexfc_resolve_learned_noalloc if noalloc else self.lib.hexfc_resolve_learned
+        self._check(fn(self.ctx, ct.byref(hotspot_struct(hot)), ct.byref(style_struct(style)), _ptr(params), int(K),
+                       float(conf_min), _ptr(out), _ptr(m), self._stream()))
         return out, m
 
 

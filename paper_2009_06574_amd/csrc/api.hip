@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,6 +14,43 @@
 #include "ctx.h"
 
 using namespace hexfc;
+
+// Scratch of hexfc_resolve_learned_noalloc: the per-row staging of the
+// learned resolve (head composites, tail features, pixel ids, fallback
+// entries) for at most NOALLOC_MAX_ROWS rows.  Each GPU holds one copy from
+// the code object's load to the end of the process.  On the host the name is
+// only a stand-in: kernels get the device address hipGetSymbolAddress returns.
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+static_assert(NOALLOC_MAX_ROWS == HEXFC_NOALLOC_MAX_ROWS, "static scratch size as declared");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices];  // per device, looked up once with that device current
+
+// Device address of the current device's copy of scratch (device = the
+// current one); nullptr and the HIP error on failure.
+void *scratch_address(int device, hipError_t *err) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    if (!scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        scratch_dev[device] = p;
+    }
+    return scratch_dev[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -110,6 +148,12 @@ hexfc_status hexfc_create(int device, hexfc_ctx **out) {
     memset(pub, 0, sizeof(uint64_t) * (PS_COUNT + 1));
     ctx->h_pub = reinterpret_cast<volatile uint64_t *>(pub);
     resolve_min_grids(device, ctx->res_min_grid);
+    hipError_t serr = hipSuccess;
+    ctx->static_scratch = scratch_address(device, &serr);
+    if (!ctx->static_scratch) {
+        ctx->static_scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(serr);
+        (void)hipGetLastError();
+    }
     if (hipDeviceSynchronize() != hipSuccess) {  // (the counters' zeroing has landed)
         (void)hipHostFree(ctx->h_stats);
         delete ctx;

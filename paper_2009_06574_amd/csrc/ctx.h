@@ -81,6 +81,11 @@ struct hexfc_ctx {
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists
     hexfc::DevBuf l_head, l_feat, l_pix, l_fb;
+    // device address of this GPU's static scratch (allocation-free learned
+    // resolve), looked up once per device; nullptr with the reason when the
+    // lookup failed
+    void *static_scratch = nullptr;
+    std::string static_scratch_err;
     int vert_b_views = 0;  // views whose world part is initialised in vert_b
     uint64_t bin_cap = 0;
     int64_t cls_cap = 0;

@@ -728,6 +728,70 @@ void enqueue_tail_features(hexfc_ctx *ctx, const ResolveArgs &a, int K, float *h
     }
 }
 
+// Arguments of the learned resolve, checked before anything is enqueued.
+hexfc_status learned_resolve_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                    const float *params, int K, float conf_min, const float *rgba_out) {
+    TRY(learned_checks(ctx, hot, style, K));
+    if (!params || !rgba_out) FAIL(ctx, HEXFC_EINVAL, "null parameters or output");
+    if (!(conf_min >= 0.f && conf_min < 1.f)) FAIL(ctx, HEXFC_ERANGE, "conf_min must be in [0, 1)");
+    return HEXFC_OK;
+}
+
+// Per-row staging of the learned resolve (rows in class order).
+struct LearnedStaging {
+    float *head;    // [rows][4]
+    float *feat;    // [rows][NFEAT]
+    uint32_t *pix;  // [rows]
+    uint32_t *fb;   // [rows] fallback entries
+};
+
+// The learned resolve on staging of at least `rows` rows: short lists exact,
+// long ones head + predicted tail or, below the confidence threshold, the
+// exact kernels over the fallback entries.  Allocates nothing.
+hexfc_status learned_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                             const float *params, int K, float conf_min, float *rgba_out, uint8_t *mask_out,
+                             int64_t rows, const LearnedStaging &st, hipStream_t s) {
+    const Tiling &tl = ctx->tl;
+    shade_params(ctx->h_views[0].sp, hot, style);
+    TRY(set_views(ctx, 1, s));
+    ResolveArgs a = resolve_args(ctx, rgba_out, 0);
+    uint64_t *stats = ctx->stats.as<uint64_t>();
+    if (mask_out) launch_fill_u8(mask_out, (int64_t)tl.W * tl.H, 1, s);
+    launch_zero_u64(stats + ST_FB, NCLASS, s);
+    if (ctx->last_stats[ST_CLASS]) {  // short lists: exact
+        ResolveSet rs{};
+        rs.cls[0].list = ctx->cls.as<uint32_t>();
+        rs.cls[0].queue = ctx->rqueue.as<uint32_t>();
+        rs.est[0] = rs.cls[0].n_host = (uint32_t)ctx->last_stats[ST_CLASS];
+        TRY(enqueue_resolve(ctx, rs, a, s));
+    }
+    if (rows) {
+        enqueue_tail_features(ctx, a, K, st.head, st.feat, nullptr, st.pix, false, s);
+        {
+            ScopedTimer tm(ctx, s, KID_MLP);
+            launch_mlp_apply(params, st.feat, st.head, st.pix, rows, a, ctx->t_sort, K, conf_min, st.fb, stats,
+                             mask_out, s);
+        }
+        // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
+        ScopedTimer tm(ctx, s, KID_FALLBACK);
+        ResolveSet rs{};
+        int64_t base = 0;
+        for (int c = 1; c < NCLASS - 1; ++c) {
+            rs.cls[c].list = st.fb + base;
+            rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
+            rs.est[c] = rs.cls[c].n_host = (uint32_t)ctx->last_stats[ST_CLASS + c];
+            base += rs.cls[c].n_host;
+        }
+        const bool prof = ctx->prof;
+        ctx->prof = false;  // (timed as the fallback)
+        const hexfc_status rc = enqueue_resolve(ctx, rs, a, s);
+        ctx->prof = prof;
+        TRY(rc);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return HEXFC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -758,55 +822,44 @@ hexfc_status hexfc_resolve_learned(hexfc_ctx *ctx, const hexfc_hotspot *hot, con
                                    void *stream) {
     if (!ctx) return HEXFC_EINVAL;
     if (stream) ctx->last_stream = (hipStream_t)stream;
-    TRY(learned_checks(ctx, hot, style, K));
-    if (!params || !rgba_out) FAIL(ctx, HEXFC_EINVAL, "null parameters or output");
-    if (!(conf_min >= 0.f && conf_min < 1.f)) FAIL(ctx, HEXFC_ERANGE, "conf_min must be in [0, 1)");
-    hipStream_t s = (hipStream_t)stream;
-    const Tiling &tl = ctx->tl;
+    TRY(learned_resolve_checks(ctx, hot, style, params, K, conf_min, rgba_out));
     const int64_t rows = learned_rows(ctx);
     TRY(grow(ctx, ctx->l_head, sizeof(float4) * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_feat, sizeof(float) * NFEAT * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_pix, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
     TRY(grow(ctx, ctx->l_fb, sizeof(uint32_t) * std::max<int64_t>(rows, 1)));
-    shade_params(ctx->h_views[0].sp, hot, style);
-    TRY(set_views(ctx, 1, s));
-    ResolveArgs a = resolve_args(ctx, rgba_out, 0);
-    uint64_t *stats = ctx->stats.as<uint64_t>();
-    if (mask_out) launch_fill_u8(mask_out, (int64_t)tl.W * tl.H, 1, s);
-    launch_zero_u64(stats + ST_FB, NCLASS, s);
-    if (ctx->last_stats[ST_CLASS]) {  // short lists: exact
-        ResolveSet rs{};
-        rs.cls[0].list = ctx->cls.as<uint32_t>();
-        rs.cls[0].queue = ctx->rqueue.as<uint32_t>();
-        rs.est[0] = rs.cls[0].n_host = (uint32_t)ctx->last_stats[ST_CLASS];
-        TRY(enqueue_resolve(ctx, rs, a, s));
-    }
-    if (rows) {
-        float *head = ctx->l_head.as<float>(), *feat = ctx->l_feat.as<float>();
-        uint32_t *pix = ctx->l_pix.as<uint32_t>(), *fb = ctx->l_fb.as<uint32_t>();
-        enqueue_tail_features(ctx, a, K, head, feat, nullptr, pix, false, s);
-        {
-            ScopedTimer tm(ctx, s, KID_MLP);
-            launch_mlp_apply(params, feat, head, pix, rows, a, ctx->t_sort, K, conf_min, fb, stats, mask_out, s);
-        }
-        // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
-        ScopedTimer tm(ctx, s, KID_FALLBACK);
-        ResolveSet rs{};
-        int64_t base = 0;
-        for (int c = 1; c < NCLASS - 1; ++c) {
-            rs.cls[c].list = fb + base;
-            rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
-            rs.est[c] = rs.cls[c].n_host = (uint32_t)ctx->last_stats[ST_CLASS + c];
-            base += rs.cls[c].n_host;
-        }
-        const bool prof = ctx->prof;
-        ctx->prof = false;  // (timed as the fallback)
-        const hexfc_status st = enqueue_resolve(ctx, rs, a, s);
-        ctx->prof = prof;
-        TRY(st);
-    }
-    HIPCHK(ctx, hipGetLastError());
-    return HEXFC_OK;
+    const LearnedStaging st{ctx->l_head.as<float>(), ctx->l_feat.as<float>(), ctx->l_pix.as<uint32_t>(),
+                            ctx->l_fb.as<uint32_t>()};
+    return learned_resolve(ctx, hot, style, params, K, conf_min, rgba_out, mask_out, rows, st, (hipStream_t)stream);
+}
+
+hexfc_status hexfc_resolve_learned_noalloc(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexfc_style *style,
+                                           const float *params, int K, float conf_min, float *rgba_out,
+                                           uint8_t *mask_out, void *stream) {
+    if (!ctx) return HEXFC_EINVAL;
+    if (stream) ctx->last_stream = (hipStream_t)stream;
+    TRY(learned_resolve_checks(ctx, hot, style, params, K, conf_min, rgba_out));
+    if (!ctx->static_scratch) FAIL(ctx, HEXFC_EDEVICE, "%s", ctx->static_scratch_err.c_str());
+    const int64_t rows = learned_rows(ctx);
+    if (rows > NOALLOC_MAX_ROWS)
+        FAIL(ctx, HEXFC_EOVERFLOW, "%lld long-list pixels exceed the static scratch of %lld rows", (long long)rows,
+             (long long)NOALLOC_MAX_ROWS);
+    // the static array carved as in the allocating call, for the maximum row
+    // count (every offset a multiple of 256 bytes); no entry of it has to
+    // start at zero: each row's staging is written before it is read
+    uint8_t *base = static_cast<uint8_t *>(ctx->static_scratch);
+    const int64_t R = NOALLOC_MAX_ROWS;
+    const LearnedStaging st{reinterpret_cast<float *>(base), reinterpret_cast<float *>(base + 16 * R),
+                            reinterpret_cast<uint32_t *>(base + (16 + 4 * NFEAT) * R),
+                            reinterpret_cast<uint32_t *>(base + (20 + 4 * NFEAT) * R)};
+    static_assert((16 + 4 * NFEAT + 8) == LEARNED_ROW_BYTES, "row staging layout");
+    // no timing events either (creating one may allocate)
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    const hexfc_status rc =
+        learned_resolve(ctx, hot, style, params, K, conf_min, rgba_out, mask_out, rows, st, (hipStream_t)stream);
+    ctx->prof = prof;
+    return rc;
 }
 
 // ------------------------------------------------------------------ autotuner

@@ -260,6 +260,12 @@ void launch_resolve_class(int c, const ClassWork &w, uint32_t est, int t_sort, c
 // when target != nullptr, the exact composite of the tail (target[4]); row j
 // of the outputs is pixel pix_list[j], stored at out_base + j.
 constexpr int NFEAT = 9;
+// Per-row staging of the learned resolve: head RGBA, NFEAT features, pixel
+// id and fallback entry.  The allocation-free variant keeps it in a static
+// device array of NOALLOC_MAX_ROWS rows.
+constexpr int64_t LEARNED_ROW_BYTES = sizeof(float) * (4 + NFEAT) + 2 * sizeof(uint32_t);
+constexpr int64_t NOALLOC_MAX_ROWS = int64_t(1) << 20;  // HEXFC_NOALLOC_MAX_ROWS
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)(NOALLOC_MAX_ROWS * LEARNED_ROW_BYTES);
 // pix_out receives the global tile-major pixel id, or with rowmajor the
 // image index (view * H + y) * W + x.
 void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a,
