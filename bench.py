@@ -27,26 +27,51 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(mesh, cams, hots, styles, row_step: int):
-    """Time the FP64 oracle (as it stands) on every `row_step`-th row of the given views."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mesh, cams, hots, styles, row_step: int, single_row_step: int = 24):
+    """Time the FP64 oracle (as it stands) on every `row_step`-th row of the
+    given views with all its threads, and on every `single_row_step`-th row of
+    the first view with one thread."""
     import numpy as np
 
     import oracle
     om = oracle.Mesh.from_synth(mesh)
-    frags, npx, dt = 0, 0, 0.0
-    for cam, hot, style in zip(cams, hots, styles):
-        W, H = cam.width, cam.height
-        rows = np.arange(0, H, row_step)
-        pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int32)
-        t0 = time.perf_counter()
-        fr = oracle.Frame.from_camera(om, cam, pixels=pix)
-        fr.shade(hot, style)
-        dt += time.perf_counter() - t0
-        frags += fr.nfrag
-        npx += pix.size
-    return dict(value=frags / dt, unit="fragments/s", cores=oracle.num_threads(), kind="oracle",
+
+    def run(views, step):
+        frags, npx, dt = 0, 0, 0.0
+        for cam, hot, style in views:
+            W, H = cam.width, cam.height
+            rows = np.arange(0, H, step)
+            pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int32)
+            t0 = time.perf_counter()
+            fr = oracle.Frame.from_camera(om, cam, pixels=pix)
+            fr.shade(hot, style)
+            dt += time.perf_counter() - t0
+            frags += fr.nfrag
+            npx += pix.size
+        return frags, npx, dt
+
+    views = list(zip(cams, hots, styles))
+    threads = oracle.num_threads()
+    frags, npx, dt = run(views, row_step)
+    oracle.set_num_threads(1)
+    f1, n1, d1 = run(views[:1], single_row_step)
+    oracle.set_num_threads(threads)
+    return dict(value=frags / dt, unit="fragments/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
                 sample=f"views 0-{len(cams) - 1}, every {row_step}th row ({npx} pixels, {frags} fragments), "
                        f"{dt:.1f} s of raster + sort + shade + blend; mesh attribute preprocessing excluded",
+                single_thread=dict(value=f1 / d1, unit="fragments/s", cores=1,
+                                   sample=f"view 0, every {single_row_step}th row ({n1} pixels, {f1} fragments), "
+                                          f"{d1:.1f} s"),
                 seconds=dt)
 
 
@@ -301,7 +326,8 @@ def main():
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(mesh, cams[:args.cpu_views], hots[:args.cpu_views], styles[:args.cpu_views],
                            args.cpu_row_step)
-        log(f"[bench] oracle {cpu['value'] / 1e6:.2f} M fragments/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+        log(f"[bench] oracle {cpu['value'] / 1e6:.2f} M fragments/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s), "
+            f"{cpu['single_thread']['value'] / 1e6:.2f} M fragments/s on one thread; {cpu['cpu_model']}")
         cpu.pop("seconds")
 
     line = {

@@ -18,7 +18,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hexfc_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HEXFC_ORACLE_LIB: another build of hexfc_oracle.c to load (the sanitizer
+# test runs the oracle from an ASan/UBSan build)
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("HEXFC_ORACLE_LIB") or _DEFAULT_LIB
 _lib = None
 
 # style vector layout shared with hexfc_oracle.c (ST_* enum)
@@ -27,12 +30,12 @@ STYLE_FIELDS = ("w_base", "k_focus", "halo_width", "halo_alpha", "darken", "acce
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+    if force or not os.path.exists(_DEFAULT_LIB):
+        tmp = _DEFAULT_LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, _DEFAULT_LIB)
+    return _DEFAULT_LIB
 
 
 def _load():
@@ -40,6 +43,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB):
+        if _LIB != _DEFAULT_LIB:
+            raise OracleError(f"no oracle library at {_LIB}")
         build()
     lib = ct.CDLL(_LIB)
     P = ct.c_void_p
@@ -54,6 +59,8 @@ def _load():
     lib.orc_scaled_jacobian.restype = ct.c_double
     lib.orc_smoothstep.argtypes = [ct.c_double, ct.c_double, ct.c_double]
     lib.orc_smoothstep.restype = ct.c_double
+    lib.orc_set_num_threads.argtypes = [ct.c_int]
+    lib.orc_set_num_threads.restype = None
     lib.orc_frame_raster.argtypes = [P, P, ct.c_int, ct.c_int, i64, P, ct.POINTER(P)]
     lib.orc_frame_raster.restype = ct.c_int
     lib.orc_frame_free.argtypes = [P]
@@ -114,6 +121,11 @@ def smoothstep(e0, e1, x) -> float:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from here on."""
+    _load().orc_set_num_threads(int(n))
 
 
 # moment-based transparency: bias towards the reference moments and the

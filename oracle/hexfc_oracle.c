@@ -813,6 +813,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the oracle's parallel loops from here on (n >= 1). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- learned tail
  * Head/tail split of a sorted list (the approximate-compositing direction of
  * Section 8): the first K fragments are blended exactly (head); the tail
