@@ -139,7 +139,7 @@ def batch_views(reps: int = 10):
                 speedup_vs_one_at_a_time=round(ms_single / ms_batch, 3))
 
 
-def learned_tail(r, mesh, conf_min, seeds=range(1001, 1005)):
+def learned_tail(r, mesh, conf_min, seeds=range(1001, 1017)):
     """Exact vs learned-tail resolve on the same lists: held-out random views
     of the benchmark mesh (the network was trained on seeds 1-1000)."""
     import numpy as np

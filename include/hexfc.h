@@ -324,7 +324,10 @@ hexfc_status hexfc_resolve_approx(hexfc_ctx *ctx, const hexfc_hotspot *hot, cons
  * confidence 1 - (1 - A_head) * (1 - sigmoid(y[4])) is at least conf_min
  * (the prediction is trusted, or the head hides the tail), else the pixel is
  * resolved by the exact kernels (fallback; its result is then bit-identical
- * to hexfc_resolve's).
+ * to hexfc_resolve's).  For K <= 16 the head is found by a top-K selection
+ * without sorting the list, and a pixel whose head is opaque to within 2^-20
+ * (where the exact resolve stops too) and at least conf_min is finished with
+ * the head alone (mask 0): its tail is neither sorted nor evaluated.
  *   params      device float[5143] (see above)
  *   K           head length, 1..64
  *   conf_min    confidence threshold in [0, 1); 0 accepts every prediction

@@ -130,7 +130,7 @@ hexfc_status hexfc_create(int device, hexfc_ctx **out) {
         hipHostMalloc((void **)&ctx->h_stats, sizeof(uint64_t) * ST_COUNT, hipHostMallocDefault) != hipSuccess ||
         ctx->stats.ensure(sizeof(uint64_t) * ST_COUNT) != hipSuccess ||
         ctx->persist.ensure(sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
-        ctx->rqueue.ensure(sizeof(uint32_t) * NCLASS * 8 * QUEUE_STRIDE) != hipSuccess ||
+        ctx->rqueue.ensure(sizeof(uint32_t) * NCLASS * QUEUE_SEGS * QUEUE_STRIDE) != hipSuccess ||
         hipMemset(ctx->persist.p, 0, sizeof(uint64_t) * PS_COUNT) != hipSuccess ||
         hipHostMalloc(&pub, sizeof(uint64_t) * (PS_COUNT + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||

@@ -327,7 +327,7 @@ ResolveSet pass_set(hexfc_ctx *ctx, int k) {
         rs.cls[c].list = ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap;
         rs.cls[c].n_dev = ctx->stats.as<uint64_t>() + ST_PCLASS + k * NCLASS + c;
         rs.cls[c].n_host = 0;
-        rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
+        rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * QUEUE_SEGS * QUEUE_STRIDE;
     }
     class_estimates(ctx, k, rs.est);
     return rs;
@@ -338,7 +338,7 @@ ResolveSet pass_set(hexfc_ctx *ctx, int k) {
 // first on both.  Classes known to be empty are not launched.
 hexfc_status enqueue_resolve(hexfc_ctx *ctx, const ResolveSet &rs, const ResolveArgs &a, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_RESOLVE);
-    launch_zero_u32(ctx->rqueue.as<uint32_t>(), NCLASS * 8 * QUEUE_STRIDE, s);  // the classes' work queues
+    launch_zero_u32(ctx->rqueue.as<uint32_t>(), NCLASS * QUEUE_SEGS * QUEUE_STRIDE, s);  // the classes' work queues
     auto used = [&](int c) { return rs.cls[c].n_dev != nullptr || rs.cls[c].n_host != 0; };
     const bool side = used(4) || used(5) || used(6) || used(7);
     if (side) {
@@ -716,14 +716,16 @@ hexfc_status learned_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexf
 }
 
 // Head composites and tail features of every long-list pixel, rows in class order.
+// With a.rgba set (the learned resolve), rows whose head hides the tail get
+// their final colour here (conf_min, mask: as the resolve's).
 void enqueue_tail_features(hexfc_ctx *ctx, const ResolveArgs &a, int K, float *head, float *feat, float *target,
-                           uint32_t *pix, bool rowmajor, hipStream_t s) {
+                           uint32_t *pix, bool rowmajor, float conf_min, uint8_t *mask, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_TAIL);
     int64_t base = 0;
     for (int c = 1; c < NCLASS - 1; ++c) {
         const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
         launch_tail_features(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap, nc, K, a, head, feat, target, pix,
-                             rowmajor, base, s);
+                             rowmajor, base, conf_min, mask, s);
         base += nc;
     }
 }
@@ -766,21 +768,30 @@ hexfc_status learned_resolve(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hex
         TRY(enqueue_resolve(ctx, rs, a, s));
     }
     if (rows) {
-        enqueue_tail_features(ctx, a, K, st.head, st.feat, nullptr, st.pix, false, s);
-        {
-            ScopedTimer tm(ctx, s, KID_MLP);
-            launch_mlp_apply(params, st.feat, st.head, st.pix, rows, a, ctx->t_sort, K, conf_min, st.fb, stats,
-                             mask_out, s);
-        }
-        // exact resolve of the fallback pixels: the rows of each class, learned ones skipped
-        ScopedTimer tm(ctx, s, KID_FALLBACK);
-        ResolveSet rs{};
+        enqueue_tail_features(ctx, a, K, st.head, st.feat, nullptr, st.pix, false, conf_min, mask_out, s);
+        // fallback list of class c: the segment of the class's rows
+        FallbackBase fbb{};
         int64_t base = 0;
         for (int c = 1; c < NCLASS - 1; ++c) {
-            rs.cls[c].list = st.fb + base;
-            rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * 8 * QUEUE_STRIDE;
-            rs.est[c] = rs.cls[c].n_host = (uint32_t)ctx->last_stats[ST_CLASS + c];
-            base += rs.cls[c].n_host;
+            fbb.b[c] = base;
+            base += (int64_t)ctx->last_stats[ST_CLASS + c];
+        }
+        {
+            ScopedTimer tm(ctx, s, KID_MLP);
+            launch_mlp_apply(params, st.feat, st.head, st.pix, rows, a, ctx->t_sort, K, conf_min, st.fb, fbb, stats,
+                             mask_out, s);
+        }
+        // exact resolve of the fallback pixels, their number per class read
+        // on the device (the grids are sized for the class's rows)
+        ScopedTimer tm(ctx, s, KID_FALLBACK);
+        ResolveSet rs{};
+        for (int c = 1; c < NCLASS - 1; ++c) {
+            const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
+            if (!nc) continue;
+            rs.cls[c].list = st.fb + fbb.b[c];
+            rs.cls[c].n_dev = stats + ST_FB + c;
+            rs.cls[c].queue = ctx->rqueue.as<uint32_t>() + c * QUEUE_SEGS * QUEUE_STRIDE;
+            rs.est[c] = nc;
         }
         const bool prof = ctx->prof;
         ctx->prof = false;  // (timed as the fallback)
@@ -812,7 +823,7 @@ hexfc_status hexfc_learned_features(hexfc_ctx *ctx, const hexfc_hotspot *hot, co
     shade_params(ctx->h_views[0].sp, hot, style);
     TRY(set_views(ctx, 1, s));
     ResolveArgs a = resolve_args(ctx, nullptr, 0);
-    enqueue_tail_features(ctx, a, K, head_out, feat_out, target_out, pix_out, true, s);
+    enqueue_tail_features(ctx, a, K, head_out, feat_out, target_out, pix_out, true, 0.f, nullptr, s);
     HIPCHK(ctx, hipGetLastError());
     return HEXFC_OK;
 }

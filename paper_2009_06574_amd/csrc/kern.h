@@ -243,9 +243,10 @@ struct ClassWork {
     const uint32_t *list;
     const uint64_t *n_dev;
     uint32_t n_host;
-    uint32_t *queue;  // 8 * QUEUE_STRIDE u32 of work-queue counters, zero at launch
+    uint32_t *queue;  // QUEUE_SEGS * QUEUE_STRIDE u32 of work-queue counters, zero at launch
 };
 constexpr int QUEUE_STRIDE = 32;  // one counter per 128-byte line
+constexpr int QUEUE_SEGS = 8;     // work-queue segments per class (a multiple of the 8 XCDs)
 // Resolve of class c (see NCLASS).  est: the class size when the host knows
 // it (a smaller grid for a short list), else ~0u (a resident grid); the
 // kernel takes the true size from device memory either way.
@@ -267,10 +268,12 @@ constexpr int64_t LEARNED_ROW_BYTES = sizeof(float) * (4 + NFEAT) + 2 * sizeof(u
 constexpr int64_t NOALLOC_MAX_ROWS = int64_t(1) << 20;  // HEXFC_NOALLOC_MAX_ROWS
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)(NOALLOC_MAX_ROWS * LEARNED_ROW_BYTES);
 // pix_out receives the global tile-major pixel id, or with rowmajor the
-// image index (view * H + y) * W + x.
+// image index (view * H + y) * W + x.  With a.rgba set (the learned resolve)
+// a pixel whose head is opaque to within 2^-20 and at least conf_min gets
+// its final colour here (mask 0) and pix_out PIX_SKIP.
 void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a,
                           float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
-                          int64_t out_base, hipStream_t s);
+                          int64_t out_base, float conf_min, uint8_t *mask, hipStream_t s);
 
 // Silhouettes of the boundary surface: per pixel of the pass's tiles
 // (device range pass_tiles[0..1]; the grid covers the nv views' tiles) the
@@ -301,14 +304,18 @@ void launch_mlp_backward(const float *params, const float *X, const float *dY, i
                          hipStream_t s);
 void launch_adam(float *w, float *m, float *v, const float *g, int count, float lr, float b1, float b2, float eps,
                  int step, hipStream_t s);
-// Apply the network to n learned pixels and compose with their heads.  fb[j]
-// receives pix[j] where row j needs the exact resolve (at most K fragments,
-// or confidence below conf_min), else PIX_SKIP; stats[ST_FB + c] counts the
-// fallback pixels of length class c; mask (nullable) gets 0 where the learned
-// tail was used.
+// Apply the network to the n rows (rows with pix PIX_SKIP are skipped) and
+// compose with their heads.  A row that needs the exact resolve (at most K
+// fragments, or confidence below conf_min) is appended to the fallback list
+// of its length class c, fb[fb_base.b[c] + i], i counted in stats[ST_FB + c]
+// (zero at launch; the list of class c has room for the class's rows); mask
+// (nullable) gets 0 where the learned tail was used.
+struct FallbackBase {
+    int64_t b[NCLASS];
+};
 void launch_mlp_apply(const float *params, const float *feat, const float *head, const uint32_t *pix, int64_t n,
-                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, uint64_t *stats,
-                      uint8_t *mask, hipStream_t s);
+                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb,
+                      const FallbackBase &fb_base, uint64_t *stats, uint8_t *mask, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 }  // namespace hexfc

@@ -348,23 +348,25 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 }
 
 // ------------------------------------------------------------------ inference in the learned resolve
-// Row j: pixel pix[j] (global tile-major id) with head composite head[j] and
-// features feat[j].  The network's tail is composed under the head when the
-// list is longer than K and the pixel confidence
-// 1 - (1 - A_head) (1 - sigmoid(y_4)) reaches conf_min; else fb[j] names the
-// pixel for the exact resolve.  mask (nullable, preset to 1 = exact) gets 0
-// where the learned tail was used.
+// Row j: pixel pix[j] (global tile-major id; PIX_SKIP for a row the head
+// already resolved) with head composite head[j] and features feat[j].  The
+// network's tail is composed under the head when the list is longer than K
+// and the pixel confidence 1 - (1 - A_head) (1 - sigmoid(y_4)) reaches
+// conf_min; else the pixel is appended to the fallback list of its length
+// class c, fb[fb_base.b[c] + i] with i counted in stats[ST_FB + c] (at most
+// the class's row count), for the exact resolve.  mask (nullable, preset to
+// 1 = exact) gets 0 where the learned tail was used.
 __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ params, const float *__restrict__ feat,
                                                    const float *__restrict__ head, const uint32_t *__restrict__ pix,
                                                    int64_t n, ResolveArgs a, int t_sort, int K, float conf_min,
-                                                   uint32_t *__restrict__ fb, uint64_t *__restrict__ stats,
-                                                   uint8_t *__restrict__ mask) {
+                                                   uint32_t *__restrict__ fb, FallbackBase fb_base,
+                                                   uint64_t *__restrict__ stats, uint8_t *__restrict__ mask) {
     __shared__ MlpLds L;
     mlp_load<false>(L, params);
     __syncthreads();
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    uint32_t nfb[NCLASS - 2] = {0, 0, 0, 0, 0, 0};  // fallback pixels per long-list class (wave total)
+    const uint64_t below = (1ull << lane) - 1;  // lanes under this one
     for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t * 16 < n; t += waves) {
         const int64_t row = t * 16 + r;
         const bool valid = row < n;
@@ -374,11 +376,11 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         mlp_fwd16(L, xb, f);
         const float logit = __shfl(f.y[0], 16 + r);  // output 4 of row r lives in lane 16 + r
         // lanes 0..15 own the 16 rows of the tile
-        const bool active = q == 0 && valid;
-        uint32_t p = 0, cnt = 0;
+        uint32_t p = PIX_SKIP, cnt = 0;
         float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q == 0 && valid) p = pix[row];
+        const bool active = p != PIX_SKIP;
         if (active) {
-            p = pix[row];
             cnt = a.count[p];
             h = reinterpret_cast<const float4 *>(head)[row];
         }
@@ -389,10 +391,16 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         const bool fallback = active && (cnt <= (uint32_t)K || !(conf >= conf_min));
         const int c = fallback ? length_class(cnt, t_sort) : -1;
 #pragma unroll
-        for (int cc = 1; cc < NCLASS - 1; ++cc) nfb[cc - 1] += (uint32_t)__popcll(__ballot(c == cc));
-        if (!active) continue;
-        fb[row] = fallback ? p : PIX_SKIP;
-        if (fallback) continue;
+        for (int cc = 1; cc < NCLASS - 1; ++cc) {
+            const uint64_t b = __ballot(c == cc);
+            if (!b) continue;
+            const int leader = __builtin_ctzll(b);
+            uint64_t at = 0;
+            if (lane == leader) at = atomicAdd((unsigned long long *)&stats[ST_FB + cc], (unsigned long long)__popcll(b));
+            at = __shfl(at, leader);
+            if (c == cc) fb[fb_base.b[cc] + at + __popcll(b & below)] = p;
+        }
+        if (!active || fallback) continue;
         const PixelRef pr = pixel_ref(a.tl, p);
         const int64_t o = (pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x;
         const float4 tail = make_float4(fminf(fmaxf(f.y[0], 0.f), 1.f), fminf(fmaxf(f.y[1], 0.f), 1.f),
@@ -405,10 +413,6 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         reinterpret_cast<float4 *>(a.rgba)[o] =
             make_float4(C0 + Tb * sp.bg[0], C1 + Tb * sp.bg[1], C2 + Tb * sp.bg[2], A);
     }
-    if (lane == 0)
-#pragma unroll
-        for (int cc = 1; cc < NCLASS - 1; ++cc)
-            if (nfb[cc - 1]) atomicAdd((unsigned long long *)&stats[ST_FB + cc], (unsigned long long)nfb[cc - 1]);
 }
 
 __global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
@@ -442,11 +446,11 @@ void launch_adam(float *w, float *m, float *v, const float *g, int count, float 
     k_adam<<<(count + 255) / 256, 256, 0, s>>>(w, m, v, g, count, lr, b1, b2, eps, c1, c2);
 }
 void launch_mlp_apply(const float *params, const float *feat, const float *head, const uint32_t *pix, int64_t n,
-                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb, uint64_t *stats,
-                      uint8_t *mask, hipStream_t s) {
+                      const ResolveArgs &a, int t_sort, int K, float conf_min, uint32_t *fb,
+                      const FallbackBase &fb_base, uint64_t *stats, uint8_t *mask, hipStream_t s) {
     if (n <= 0) return;
     k_mlp_apply<<<grid_for((n + 15) / 16, 4), 256, 0, s>>>(params, feat, head, pix, n, a, t_sort, K, conf_min, fb,
-                                                            stats, mask);
+                                                            fb_base, stats, mask);
 }
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
     if (n <= 0) return;

@@ -569,19 +569,23 @@ __device__ __forceinline__ uint32_t class_size(const ClassWork &w) {
 // Dynamic distribution of a class list over the resident waves (what a grid
 // of one workgroup per list item would get from the hardware dispatcher,
 // without knowing the list's size when the grid is launched).  The list is
-// cut into 8 contiguous segments, one per XCD (workgroups are dealt to the
-// XCDs round-robin, and an XCD's waves share an L2 in which neighbouring
-// pixels find the faces they shade); a wave pops the next item of its XCD's
-// segment, with the next pop in flight while it works on the current one,
-// then helps with what is left of the other segments.  `body(item)` is
-// called by the whole wave with a wave-uniform item.
+// cut into 8 contiguous parts, one per XCD (workgroups are dealt to the XCDs
+// round-robin, and an XCD's waves share an L2 in which neighbouring pixels
+// find the faces they shade), each part into QUEUE_SEGS / 8 segments with a
+// counter of their own (pops on one address serialise); a wave pops the next
+// item of its home segment, with the next pop in flight while it works on the
+// current one, then helps with what is left of its XCD's other segments and
+// then of the other XCDs'.  `body(item)` is called by the whole wave with a
+// wave-uniform item.
 template <int PER_POP, class Body>
 __device__ __forceinline__ void drain(uint32_t total, uint32_t *__restrict__ queue, int lane, Body &&body) {
-    const int xcd = blockIdx.x & 7;
+    constexpr int SUB = QUEUE_SEGS / 8;
+    const int xcd = blockIdx.x & 7, sub = (blockIdx.x >> 3) % SUB;
 #pragma unroll 1
-    for (int h = 0; h < 8; ++h) {
-        const int x = (xcd + h) & 7;
-        const uint32_t lo = (uint32_t)((uint64_t)total * x / 8), hi = (uint32_t)((uint64_t)total * (x + 1) / 8);
+    for (int h = 0; h < QUEUE_SEGS; ++h) {
+        const int x = ((xcd + h / SUB) & 7) * SUB + (sub + h) % SUB;
+        const uint32_t lo = (uint32_t)((uint64_t)total * x / QUEUE_SEGS),
+                       hi = (uint32_t)((uint64_t)total * (x + 1) / QUEUE_SEGS);
         uint32_t *ctr = queue + x * QUEUE_STRIDE;
         if (lo == hi || (h && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo))
             continue;  // (an empty segment, or one already taken)
@@ -710,27 +714,126 @@ void launch_resolve_class(int c, const ClassWork &w, uint32_t est, int t_sort, c
 }
 
 // ------------------------------------------------------------------ learned tail: head and tail features
-// Wave per pixel, as the long-list resolve: sort; the first K fragments are
-// moved to lanes 0..K-1, shaded exactly (one per lane) and composited in
-// order (head).  Every tail fragment gets the proxy shading of its face
-// (opacity from the mean corner importance and the focus factor at the face
-// centre, colour from the mean corner importance) from which the features
-// are accumulated: tail length, proxy opacity sum, opacity-weighted mean depth
+// Wave per pixel, as the long-list resolve.  The head (the first K fragments
+// in list order) is shaded exactly, one fragment per lane, and composited in
+// order.  Every tail fragment gets the proxy shading of its face (opacity
+// from the mean corner importance and the focus factor at the face centre,
+// colour from the mean corner importance) from which the features are
+// accumulated: tail length, proxy opacity sum, opacity-weighted mean depth
 // and mean squared depth, the ordered composite of the proxies and the depth
-// where the tail starts.  With TRAIN the tail is also shaded exactly and
-// composited (the regression target).
+// where the tail starts.
+//   TAIL_FEATURES  every row gets its head and features (full sort)
+//   TAIL_TRAIN     as TAIL_FEATURES, plus the exact composite of the tail
+//                  (the regression target)
+//   TAIL_RESOLVE   the learned resolve: the head comes from a selection of
+//                  the K smallest records (no sort); a pixel whose head is opaque to
+//                  within 2^-20 (and at least conf_min, so that its confidence
+//                  accepts it whatever the network says) gets the head over
+//                  the background as its final colour, mask 0 and no row
+//                  (pix PIX_SKIP, zero features): its tail is invisible.  Only
+//                  the other pixels sort the whole list for the ordered proxy.
+enum { TAIL_FEATURES = 0, TAIL_TRAIN = 1, TAIL_RESOLVE = 2 };
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-template <int R, bool TRAIN>
+// The head of a list without sorting it: the m = min(K, n) smallest records
+// of the wave's 64 R keys (element e = lane R + r in v[r], padding ~0; the
+// records of a list are distinct), ascending, one per lane: lane l < m gets
+// the l-th smallest in `h`.  A bitwise search over the 25-bit high words
+// (counting with ballots) finds the high word h* of the K-th smallest; the
+// keys below it are in the head, and of those equal to it the ones with the
+// smallest low words (a second search, only when more of them tie than there
+// are places left).  The m chosen keys are compacted through the wave's LDS
+// `stash` (2 KK words) and ranked by comparing each with all the others.
+template <int R, int KK>
+__device__ __forceinline__ uint32_t wave_head(const uint64_t (&v)[R], uint32_t n, int K, int lane,
+                                              uint64_t *__restrict__ stash, uint64_t &h) {
+    const uint32_t m = min((uint32_t)K, n);
+    uint32_t hi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) hi[r] = (uint32_t)(v[r] >> 32);
+    auto count_below = [&](uint32_t t) {  // keys whose high word is below t (wave-uniform)
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__ballot(hi[r] < t));
+        return c;
+    };
+    uint32_t hs = 0;
+    for (int b = 24; b >= 0; --b) {
+        const uint32_t t = hs | (1u << b);
+        if (count_below(t) < m) hs = t;
+    }
+    // places left for keys with high word hs, and how many there are
+    const uint32_t less = count_below(hs);
+    uint32_t eq = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) eq += (uint32_t)__popcll(__ballot(hi[r] == hs));
+    const uint32_t need = m - less;
+    uint32_t lo_cut = 0xffffffffu;  // keys with high word hs and low word <= lo_cut are in
+    if (eq > need) {
+        uint32_t ls = 0;
+        for (int b = 31; b >= 0; --b) {
+            const uint32_t t = ls | (1u << b);
+            uint32_t c = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__ballot(hi[r] == hs && (uint32_t)v[r] < t));
+            if (c < need) ls = t;
+        }
+        lo_cut = ls;  // the need-th smallest low word among the ties
+    }
+    // compact the chosen keys into stash[0..m-1] (any order)
+    const uint64_t below = (1ull << lane) - 1;
+    uint32_t base = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool in = hi[r] < hs || (hi[r] == hs && (uint32_t)v[r] <= lo_cut && (lane * R + r) < (int)n);
+        const uint64_t bal = __ballot(in);
+        if (in) stash[base + __popcll(bal & below)] = v[r];
+        base += (uint32_t)__popcll(bal);
+    }
+    wave_lds_sync();
+    // rank: lane l < m places its key at its position in ascending order
+    uint64_t mine = ~0ull;
+    uint32_t rank = 0;
+    if ((uint32_t)lane < m) {
+        mine = stash[lane];
+        for (uint32_t j = 0; j < m; ++j) rank += stash[j] < mine;
+    }
+    if ((uint32_t)lane < m) stash[KK + rank] = mine;
+    wave_lds_sync();
+    h = (uint32_t)lane < m ? stash[KK + lane] : ~0ull;
+    wave_lds_sync();  // (the stash is rewritten by the wave's next list)
+    return m;
+}
+
+// Head composite of pixel pr from the head key h of lane l < m (element l
+// in list order); the result is uniform over the wave.
+__device__ __forceinline__ float4 head_composite(const ResolveArgs &a, const PixelRef &pr, uint64_t h, uint32_t m,
+                                                 int lane) {
+    float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
+    if ((uint32_t)lane < m) {
+        const ViewParams &vp = a.views[pr.view];
+        const Frag fr = shade(a.mesh, a.mesh.vert + pr.view * a.mesh.V, vp.sp, (uint32_t)(h & 0xffffffffu), pr.x, pr.y);
+        H0 = fr.r;
+        H1 = fr.g;
+        H2 = fr.b;
+        HA = fr.a;
+    }
+    over_reduce(H0, H1, H2, HA, lane);
+    return make_float4(__shfl(H0, 0), __shfl(H1, 0), __shfl(H2, 0), __shfl(HA, 0));
+}
+
+template <int R, int MODE>
 __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restrict__ list, uint32_t npix, int K,
-                                                       ResolveArgs a, float *__restrict__ head,
+                                                       float conf_min, ResolveArgs a, float *__restrict__ head,
                                                        float *__restrict__ feat, float *__restrict__ target,
-                                                       uint32_t *__restrict__ pix_out, bool rowmajor,
-                                                       int64_t out_base) {
+                                                       uint32_t *__restrict__ pix_out, uint8_t *__restrict__ mask,
+                                                       bool rowmajor, int64_t out_base) {
+    constexpr bool TRAIN = MODE == TAIL_TRAIN;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (wave >= npix) return;
@@ -745,25 +848,52 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         const uint32_t e = lane * R + r;
         v[r] = e < n ? src[e] : ~0ull;
     }
-    bitonic_sort<R>(v, lane);
     const PixelRef pr = pixel_ref(a.tl, p);
     const ViewParams &vp = a.views[pr.view];
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
-    // head: sorted element l to lane l, one exact shade per lane
-    uint64_t hv = ~0ull;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-        const uint64_t t = __shfl(v[rr], lane / R);
-        if (lane % R == rr) hv = t;
-    }
+    const int64_t o = out_base + wave;
     float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
-    if (lane < K && (uint32_t)lane < n) {
-        const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(hv & 0xffffffffu), pr.x, pr.y);
-        H0 = fr.r;
-        H1 = fr.g;
-        H2 = fr.b;
-        HA = fr.a;
+    bool have_head = false;
+    if constexpr (MODE == TAIL_RESOLVE) {
+        __shared__ uint64_t stash[4][128];
+        uint64_t hk;
+        const uint32_t m = wave_head<R, 64>(v, n, K, lane, stash[threadIdx.x >> 6], hk);
+        const float4 h = head_composite(a, pr, hk, m, lane);
+        if (n > (uint32_t)K && 1.f - h.w < T_EPS && h.w >= conf_min) {
+            // the tail is invisible: final colour now, no row for the network
+            if (lane == 0) {
+                write_rgba(a, pr, sp, h.x, h.y, h.z, h.w);
+                if (mask) mask[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] = 0;
+                reinterpret_cast<float4 *>(head)[o] = h;
+                pix_out[o] = PIX_SKIP;
+            }
+            if (lane < NFEAT) feat[o * NFEAT + lane] = 0.f;
+            return;
+        }
+        H0 = h.x;
+        H1 = h.y;
+        H2 = h.z;
+        HA = h.w;
+        have_head = true;
+    }
+    bitonic_sort<R>(v, lane);
+    if (!have_head) {
+        // head: sorted element l to lane l, one exact shade per lane
+        uint64_t hv = ~0ull;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const uint64_t t = __shfl(v[rr], lane / R);
+            if (lane % R == rr) hv = t;
+        }
+        if (lane < K && (uint32_t)lane < n) {
+            const Frag fr = shade(a.mesh, vert, sp, (uint32_t)(hv & 0xffffffffu), pr.x, pr.y);
+            H0 = fr.r;
+            H1 = fr.g;
+            H2 = fr.b;
+            HA = fr.a;
+        }
+        over_reduce(H0, H1, H2, HA, lane);
     }
     const float zs = 1.f / (vp.w1 - vp.w0);
     float T0 = 0.f, T1 = 0.f, T2 = 0.f, TA = 0.f;  // exact tail composite (TRAIN)
@@ -799,7 +929,6 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         PA += T * al;
         if ((int)e == K) zf = z;
     }
-    over_reduce(H0, H1, H2, HA, lane);
     if (TRAIN) over_reduce(T0, T1, T2, TA, lane);
     over_reduce(P0, P1, P2, PA, lane);
     sa = wave_sum(sa);
@@ -807,7 +936,6 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     sz2 = wave_sum(sz2);
     zf = wave_sum(zf);
     if (lane == 0) {
-        const int64_t o = out_base + wave;
         const float inv = sa > 0.f ? 1.f / sa : 0.f;
         float *F = feat + o * NFEAT;
         F[0] = log1pf((float)max((int)n - K, 0));
@@ -1300,14 +1428,25 @@ void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int
 
 void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a, float *head,
                           float *feat, float *target, uint32_t *pix_out, bool rowmajor, int64_t out_base,
-                          hipStream_t s) {
+                          float conf_min, uint8_t *mask, hipStream_t s) {
     if (npix == 0) return;
     dim3 g((npix + 3) / 4);
-#define TAIL(RV)                                                                                                     \
-    if (target)                                                                                                      \
-        k_tail_features<RV, true><<<g, 256, 0, s>>>(pix_list, npix, K, a, head, feat, target, pix_out, rowmajor, out_base);    \
-    else                                                                                                             \
-        k_tail_features<RV, false><<<g, 256, 0, s>>>(pix_list, npix, K, a, head, feat, target, pix_out, rowmajor, out_base);
+    // learned resolve (an output image), training rows (a target) or feature rows
+    const int mode = a.rgba ? TAIL_RESOLVE : target ? TAIL_TRAIN : TAIL_FEATURES;
+#define TAIL(RV)                                                                                                   \
+    switch (mode) {                                                                                                \
+        case TAIL_RESOLVE:                                                                                         \
+            k_tail_features<RV, TAIL_RESOLVE><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat, target, \
+                                                                pix_out, mask, rowmajor, out_base);                \
+            break;                                                                                                 \
+        case TAIL_TRAIN:                                                                                           \
+            k_tail_features<RV, TAIL_TRAIN><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat, target,   \
+                                                              pix_out, mask, rowmajor, out_base);                  \
+            break;                                                                                                 \
+        default:                                                                                                   \
+            k_tail_features<RV, TAIL_FEATURES><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat,       \
+                                                                 target, pix_out, mask, rowmajor, out_base);       \
+    }
     switch (cls) {
         case 1: TAIL(1); break;
         case 2: TAIL(2); break;
