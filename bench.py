@@ -75,6 +75,14 @@ def cpu_baseline(mesh, cams, hots, styles, row_step: int, single_row_step: int =
                 seconds=dt)
 
 
+# kernel symbols of the timed entries (rocprofv3 names)
+KERNEL_SYMBOL = {"fill": "hexfc::k_fill<8, 8>", "count": "hexfc::k_count<8, 8>", "resolve_c0": "k_resolve_short<16>",
+                 "resolve_c1": "k_resolve_wave<1>", "resolve_c2": "k_resolve_wave<2>",
+                 "resolve_c3": "k_resolve_wave<4>", "resolve_c4": "k_resolve_wave<8>",
+                 "resolve_c5": "k_resolve_wave_wide<16>", "resolve_c6": "k_resolve_wave_wide<32>",
+                 "resolve_c7": "hexfc::k_resolve_block", "resolve": "every resolve class kernel, fork to join"}
+
+
 def measured_traffic(kernel: str):
     """Bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, scaled by the copy calibration; None when there is no
@@ -281,15 +289,21 @@ def main():
     kt = r.kernel_times()
     r.set_profiling(False)
 
-    # rooflines of the list kernels from the HIP events recorded around their
-    # launches on the render stream: the fill (8 B per fragment written, 4 B
-    # per bin entry and 8 B of offsets per pixel read), the resolve (8 B per
-    # fragment read, 32 B per pixel: count, offsets, RGBA) and the coverage
-    # count (4 B per bin entry read, 4 B per pixel written)
+    # rooflines of single kernels from the HIP events recorded around their
+    # launches on their own streams: the fill (8 B per fragment written, 4 B
+    # per bin entry and 8 B of offsets per pixel read), the coverage count
+    # (4 B per bin entry read, 4 B per pixel written) and the resolve kernel
+    # of each length class c (8 B per fragment of the class read, 32 B per
+    # pixel of the class: count, offsets, RGBA); and of the whole resolve (all
+    # classes, both streams, fork to join) for reference
     P = 1920 * 1080
+    cls_frags = [sum(view_stats[k]["class_fragments"][c] for k in seq) for c in range(8)]
+    cls_pix = [sum(view_stats[k]["classes"][c] for k in seq) for c in range(8)]
     alg = {"fill": 8.0 * frags + 4.0 * bins + 8.0 * P * args.steps,
-           "resolve": 8.0 * frags + 32.0 * P * args.steps,
-           "count": 4.0 * bins + 4.0 * P * args.steps}
+           "count": 4.0 * bins + 4.0 * P * args.steps,
+           "resolve": 8.0 * frags + 32.0 * P * args.steps}
+    for c in range(8):
+        alg[f"resolve_c{c}"] = 8.0 * cls_frags[c] + 32.0 * cls_pix[c]
     rooflines = {}
     for k, b in alg.items():
         if k not in kt:
@@ -299,13 +313,24 @@ def main():
         traffic = measured_traffic(k) if args.grid == 128 else None
         rooflines[k] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                             frac=round(ach / HBM_PEAK_GBS, 4), traffic=None if traffic is None else int(traffic),
-                            kernel=k, avg_launch_ms=round(ms_k / n_k, 4), bytes_per_launch=int(b / n_k))
-    dom = max(("fill", "resolve"), key=lambda k: kt[k][0])
+                            kernel=KERNEL_SYMBOL.get(k, k), avg_launch_ms=round(ms_k / n_k, 4),
+                            bytes_per_launch=int(b / n_k))
+    # the dominant kernel: of the single kernels that move the fragment records
+    # and run on the render stream (the fill, the resolve of classes 0-3;
+    # classes 4-7 run on a second stream and their event times include
+    # waiting), the one with the longest time per frame; the coverage count,
+    # bound by VALU issue and latency rather than by bytes, is in "others"
+    singles = [k for k in ("fill", "resolve_c0", "resolve_c1", "resolve_c2", "resolve_c3") if k in rooflines]
+    dom = max(singles, key=lambda k: kt[k][0])
     roofline = dict(rooflines[dom])
-    roofline["others"] = {k: {x: v[x] for x in ("achieved", "frac", "avg_launch_ms", "bytes_per_launch", "traffic")}
+    roofline["others"] = {k: {x: v[x] for x in ("kernel", "achieved", "frac", "avg_launch_ms", "bytes_per_launch",
+                                                "traffic")}
                           for k, v in rooflines.items() if k != dom}
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
-    log(f"[bench] per-frame kernel ms: {kernel_ms} (sum {sum(kernel_ms.values()):.3f})")
+    top = {k: v for k, v in kernel_ms.items() if not k.startswith("resolve_c")}
+    log(f"[bench] per-frame kernel ms: {top} (sum {sum(top.values()):.3f})")
+    log(f"[bench] resolve by class, ms per frame: "
+        f"{ {k: v for k, v in kernel_ms.items() if k.startswith('resolve_c')} }")
     for k, v in rooflines.items():
         log(f"[bench] {k}: {v['achieved']:.1f} GB/s ({v['frac']:.1%} of HBM peak), {v['avg_launch_ms']:.4f} ms")
 

@@ -239,10 +239,13 @@ hexfc_status hexfc_get_frame_stats(hexfc_ctx *ctx, uint64_t *out, int n);
  * the recorded events, returns the accumulated milliseconds and launch counts
  * per kernel and resets them.  Kernel index: 0 transform, 1 triangle binning
  * (count + tile scan), 2 bin scatter, 3 coverage count, 4 pixel scan,
- * 5 length classes, 6 pass plan, 7 list fill, 8 resolve (every length class,
- * one persistent launch per pass), 9 learned tail: head and features,
- * 10 learned tail: network and compose, 11 learned tail: exact fallback.
- * n = number of entries wanted (<= 12). */
+ * 5 length classes, 6 pass plan, 7 list fill, 8 resolve (every length class
+ * of a pass, both streams, fork to join), 9 learned tail: head and features,
+ * 10 learned tail: network and compose, 11 learned tail: exact fallback,
+ * 12 + c the resolve kernel of length class c alone (c = 0..7; part of 8;
+ * classes 4..7 run on a second stream, their times include waiting for the
+ * compute units the first stream holds).  n = number of entries wanted
+ * (<= 20). */
 hexfc_status hexfc_set_profiling(hexfc_ctx *ctx, int enable);
 hexfc_status hexfc_get_kernel_times(hexfc_ctx *ctx, double *ms_out, uint64_t *launches_out, int n);
 

@@ -297,7 +297,7 @@ class Renderer:
                     fallback=[int(a[24 + i]) for i in range(8)])
 
     KERNELS = ("transform", "bin_count", "bin_scatter", "count", "scan", "classify", "plan", "fill", "resolve",
-               "tail_features", "mlp_apply", "fallback")
+               "tail_features", "mlp_apply", "fallback") + tuple(f"resolve_c{c}" for c in range(8))
 
     APPROX_METHODS = {"mlab": 1, "moments": 2}
 

@@ -345,10 +345,16 @@ hexfc_status enqueue_resolve(hexfc_ctx *ctx, const ResolveSet &rs, const Resolve
         HIPCHK(ctx, hipEventRecord(ctx->ev_fork, s));
         HIPCHK(ctx, hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0));
         for (int c = NCLASS - 1; c >= 4; --c)
-            if (used(c)) launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, ctx->side_stream);
+            if (used(c)) {
+                ScopedTimer tc(ctx, ctx->side_stream, KID_RESOLVE_C0 + c);
+                launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, ctx->side_stream);
+            }
     }
     for (int c = 3; c >= 0; --c)
-        if (used(c)) launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, s);
+        if (used(c)) {
+            ScopedTimer tc(ctx, s, KID_RESOLVE_C0 + c);
+            launch_resolve_class(c, rs.cls[c], rs.est[c], ctx->t_sort, ctx->res_min_grid, a, s);
+        }
     if (side) {
         HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side_stream));
         HIPCHK(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));

@@ -63,11 +63,12 @@ enum PersistSlot {
 // kernels timed by the optional per-launch HIP-event profiler
 enum KernelId {
     KID_TRANSFORM = 0, KID_BIN_COUNT, KID_BIN_SCATTER, KID_COUNT, KID_SCAN, KID_CLASSIFY, KID_PLAN, KID_FILL,
-    KID_RESOLVE,   // the persistent resolve (every length class)
+    KID_RESOLVE,   // the resolve (every length class, both streams)
     KID_TAIL,      // learned resolve: head and tail features
     KID_MLP,       // learned resolve: network and compose
     KID_FALLBACK,  // learned resolve: exact fallback
-    KID_COUNT_
+    KID_RESOLVE_C0,  // the resolve kernel of length class c = KID_RESOLVE_C0 + c, on its own stream
+    KID_COUNT_ = KID_RESOLVE_C0 + 8
 };
 
 struct Mat3q { long long m[3][4]; };  // rows x, y, w of M_q
