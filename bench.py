@@ -315,12 +315,11 @@ def main():
                             frac=round(ach / HBM_PEAK_GBS, 4), traffic=None if traffic is None else int(traffic),
                             kernel=KERNEL_SYMBOL.get(k, k), avg_launch_ms=round(ms_k / n_k, 4),
                             bytes_per_launch=int(b / n_k))
-    # the dominant kernel: of the single kernels that move the fragment records
-    # and run on the render stream (the fill, the resolve of classes 0-3;
-    # classes 4-7 run on a second stream and their event times include
-    # waiting), the one with the longest time per frame; the coverage count,
-    # bound by VALU issue and latency rather than by bytes, is in "others"
-    singles = [k for k in ("fill", "resolve_c0", "resolve_c1", "resolve_c2", "resolve_c3") if k in rooflines]
+    # the dominant kernel: of the single kernels on the render stream (the
+    # coverage count, the fill, the resolve of classes 0-3; classes 4-7 run on
+    # a second stream and their event times include waiting), the one with the
+    # longest time per frame
+    singles = [k for k in ("count", "fill", "resolve_c0", "resolve_c1", "resolve_c2", "resolve_c3") if k in rooflines]
     dom = max(singles, key=lambda k: kt[k][0])
     roofline = dict(rooflines[dom])
     roofline["others"] = {k: {x: v[x] for x in ("kernel", "achieved", "frac", "avg_launch_ms", "bytes_per_launch",

@@ -2,22 +2,31 @@
 //
 // A 9 -> 64 -> 64 -> 5 MLP (GELU, tanh form) predicts a pixel's tail
 // composite (premultiplied RGBA) and a confidence logit from 9 tail features.
-// Inference, loss, backward and the Adam update are hand-written; every
-// matrix product is a v_mfma_f32_16x16x16_bf16 with FP32 accumulation, the
-// master weights and their gradients stay FP32.
+// Inference, loss, backward and the Adam update are hand-written on the
+// matrix cores with FP32 accumulation; the master weights and their
+// gradients stay FP32.  Products over the 64 hidden units use gfx950's
+// v_mfma_f32_16x16x32_bf16, those over 16 (the 9 inputs, the 16 rows of a
+// tile) v_mfma_f32_16x16x16_bf16.
 //
 // All products are written transposed: Z^T (units x rows) = W^T (units x in)
-// * X^T (in x rows).  With the MFMA lane layout (A[m][4*(l/16)+i],
-// B[4*(l/16)+i][l%16], D[4*(l/16)+i][l%16] for lane l) the D tile of one
-// layer (units 16*mt + 4*(l/16) + i, row l%16) is exactly the B operand of
-// the next layer's k-step mt, so forward activations never leave registers.
-// The weight gradients (sums over rows) need the row index as the reduction
-// axis and go through small per-wave LDS transposes.
+// * X^T (in x rows).  The D tile of an MFMA holds D[4*(l/16)+i][l%16] in
+// lane l, i < 4: units 16*mt + 4*(l/16) + i of row l%16.  In the 16x16x16
+// form that is exactly the B operand (4 consecutive k per lane) of the next
+// layer's k-step mt; in the 16x16x32 form a lane supplies 8 k, and two D
+// tiles side by side (mt = 2ks, 2ks + 1) give them without any lane
+// exchange, provided the weights' k axis is stored in the same order: k-step
+// ks, lane group g, slot j < 4 is unit 32ks + 4g + j and slot 4 + j is unit
+// 32ks + 16 + 4g + j (the sum over k does not depend on the order).  So
+// forward activations never leave registers.  The weight gradients (sums
+// over rows) need the row index as the reduction axis and go through small
+// per-wave LDS transposes.
 #include "kern.h"
 
 namespace hexfc {
 
 typedef __attribute__((ext_vector_type(4))) short bf4;
+typedef __attribute__((ext_vector_type(8))) short bf8;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
 typedef __attribute__((ext_vector_type(4))) float f4;
 
 constexpr int NF = 9, NH = 64, NO = 5;
@@ -32,7 +41,17 @@ __device__ __forceinline__ unsigned short f2bf(float x) {  // round to nearest e
     return (unsigned short)(u >> 16);
 }
 __device__ __forceinline__ f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
+}
 __device__ __forceinline__ bf4 ld4(const unsigned short *p) { return *reinterpret_cast<const bf4 *>(p); }
+__device__ __forceinline__ bf8 ld8(const unsigned short *p) { return *reinterpret_cast<const bf8 *>(p); }
+// the B operand of k-step ks over 64 units: D tiles 2ks and 2ks + 1 side by side
+__device__ __forceinline__ bf8 cat8(bf4 lo, bf4 hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7); }
+// hidden unit stored at column c of a weight's 64-unit k axis (see the top)
+__host__ __device__ constexpr int kunit(int c) {
+    return 32 * (c / 32) + ((c % 8) < 4 ? 4 * ((c % 32) / 8) + c % 8 : 16 + 4 * ((c % 32) / 8) + c % 8 - 4);
+}
 __device__ __forceinline__ bf4 pack4(float a, float b, float c, float d) {
     bf4 r;
     r[0] = (short)f2bf(a);
@@ -49,14 +68,15 @@ __device__ __forceinline__ float gelu_d(float x) {
     return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * GC * (1.f + 3.f * 0.044715f * x * x);
 }
 
-// BF16 weights in LDS, each in the layout its MFMA operand reads (4
-// consecutive k values per lane); FP32 biases and input standardisation.
+// BF16 weights in LDS, each in the layout its MFMA operand reads (4 or 8
+// consecutive k values per lane; a 64-unit k axis in kunit order); FP32
+// biases and input standardisation.
 struct MlpLds {
     unsigned short w1t[NH][16];  // [unit][in]       (in >= 9 zero)
-    unsigned short w2t[NH][NH];  // [out unit][in unit]
-    unsigned short w3t[16][NH];  // [out][unit]      (out >= 5 zero)
+    unsigned short w2t[NH][NH];  // [out unit][in unit, kunit order]
+    unsigned short w3t[16][NH];  // [out][unit, kunit order]  (out >= 5 zero)
     unsigned short w3[NH][16];   // [unit][out]
-    unsigned short w2[NH][NH];   // [in unit][out unit]
+    unsigned short w2[NH][NH];   // [in unit][out unit, kunit order]
     float b1[NH], b2[NH], b3[16], mu[16], is[16];
 };
 
@@ -66,13 +86,13 @@ __device__ void mlp_load(MlpLds &L, const float *__restrict__ p) {
         const int u = i / 16, k = i % 16;
         L.w1t[u][k] = k < NF ? f2bf(p[P_W1 + k * NH + u]) : 0;
         if (BWD) L.w3[u][k] = k < NO ? f2bf(p[P_W3 + u * NO + k]) : 0;
-        const int o = i / NH, uu = i % NH;
-        L.w3t[o][uu] = o < NO ? f2bf(p[P_W3 + uu * NO + o]) : 0;
+        const int o = i / NH, c = i % NH;
+        L.w3t[o][c] = o < NO ? f2bf(p[P_W3 + kunit(c) * NO + o]) : 0;
     }
     for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
-        const int a = i / NH, b = i % NH;
-        L.w2t[a][b] = f2bf(p[P_W2 + b * NH + a]);
-        if (BWD) L.w2[a][b] = f2bf(p[P_W2 + a * NH + b]);
+        const int a = i / NH, c = i % NH;
+        L.w2t[a][c] = f2bf(p[P_W2 + kunit(c) * NH + a]);
+        if (BWD) L.w2[a][c] = f2bf(p[P_W2 + a * NH + kunit(c)]);
     }
     for (int i = threadIdx.x; i < NH; i += blockDim.x) {
         L.b1[i] = p[P_B1 + i];
@@ -100,8 +120,8 @@ struct Fwd {
     f4 z1[4], z2[4], y;
 };
 
-// Forward of one 16-row tile (24 MFMAs).  Lane l: row l%16; z1/z2 hold units
-// 16*mt + 4*(l/16) + i, y holds outputs 4*(l/16) + i.
+// Forward of one 16-row tile (4 + 8 + 2 MFMAs).  Lane l: row l%16; z1/z2
+// hold units 16*mt + 4*(l/16) + i, y holds outputs 4*(l/16) + i.
 __device__ __forceinline__ void mlp_fwd16(const MlpLds &L, bf4 xb, Fwd &f) {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -119,7 +139,8 @@ __device__ __forceinline__ void mlp_fwd16(const MlpLds &L, bf4 xb, Fwd &f) {
     for (int mt = 0; mt < 4; ++mt) {
         f4 z = zero;
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) z = mfma(ld4(&L.w2t[16 * mt + r][16 * ks + 4 * q]), hb[ks], z);
+        for (int ks = 0; ks < 2; ++ks)
+            z = mfma32(ld8(&L.w2t[16 * mt + r][32 * ks + 8 * q]), cat8(hb[2 * ks], hb[2 * ks + 1]), z);
 #pragma unroll
         for (int i = 0; i < 4; ++i) z[i] += L.b2[16 * mt + 4 * q + i];
         f.z2[mt] = z;
@@ -127,7 +148,7 @@ __device__ __forceinline__ void mlp_fwd16(const MlpLds &L, bf4 xb, Fwd &f) {
     }
     f4 y = zero;
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) y = mfma(ld4(&L.w3t[r][16 * ks + 4 * q]), hb2[ks], y);
+    for (int ks = 0; ks < 2; ++ks) y = mfma32(ld8(&L.w3t[r][32 * ks + 8 * q]), cat8(hb2[2 * ks], hb2[2 * ks + 1]), y);
 #pragma unroll
     for (int i = 0; i < 4; ++i) y[i] += L.b3[4 * q + i];
     f.y = y;
@@ -281,7 +302,8 @@ __global__ void __launch_bounds__(64) k_mlp_backward(const float *__restrict__ p
         for (int mt = 0; mt < 4; ++mt) {
             f4 h = zero;
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) h = mfma(ld4(&L.w2[16 * mt + r][16 * ks + 4 * q]), bz2[ks], h);
+            for (int ks = 0; ks < 2; ++ks)
+                h = mfma32(ld8(&L.w2[16 * mt + r][32 * ks + 8 * q]), cat8(bz2[2 * ks], bz2[2 * ks + 1]), h);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 h[i] *= gelu_d(f.z1[mt][i]);
