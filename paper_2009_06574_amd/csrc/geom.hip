@@ -224,7 +224,7 @@ struct CovSetup {
     int b1, c1, a2, b2;
     int c2;
     int pad0;  // candidate pixel box in the tile: x0 | x1 << 8 | y0 << 16 | y1 << 24
-    int pad1;  // candidate pixels (0: the triangle misses the tile)
+    int pad1;  // candidate rows of the box (0: the triangle misses the tile)
     int pad2;
 };
 // Depth key of the same triangle: N(dx, dy) = n0 + na*dx + nb*dy (exact
@@ -295,7 +295,7 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
         cs.a1 = ea[1]; cs.b1 = eb[1]; cs.c1 = ec[1];
         cs.a2 = ea[2]; cs.b2 = eb[2]; cs.c2 = ec[2];
         cs.pad0 = x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
-        cs.pad1 = (x1 - x0 + 1) * (y1 - y0 + 1);
+        cs.pad1 = y1 - y0 + 1;
     }
 }
 
@@ -366,7 +366,7 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 template <int TW, int TH>
 struct RasterShape {
     static constexpr int NT = TW * TH, NW = NT / 64, S = RASTER_WG / NT;
-    static_assert(NT % 64 == 0 && RASTER_WG % NT == 0, "tile shape");
+    static_assert(NT % 64 == 0 && RASTER_WG % NT == 0 && 64 % TW == 0, "tile shape");
 };
 
 // Synchronise the lanes of one group (the NT lanes that work on one bin
@@ -403,10 +403,11 @@ __device__ __forceinline__ Chunk bin_chunk(uint64_t b0, uint64_t b1, int grp) {
     return c;
 }
 
-// Count: every batch of entries is expanded into its candidate (entry,
-// pixel) pairs -- the pixels of the tile inside the triangle's bounding box
-// -- one lane per pair; LDS atomics accumulate the per-pixel counts and the
-// entries' coverage masks.
+// Count: every batch of entries is expanded into its candidate (entry, row)
+// pairs -- the rows of the tile that cross the triangle's bounding box --
+// one lane per pair, which tests the row's pixels inside the box; LDS
+// atomics accumulate the per-pixel counts and, one per row, the entries'
+// coverage masks.
 constexpr int RASTER_WINDOW = 1024;  // candidate pairs expanded at a time per group
 
 template <int TW, int TH>
@@ -480,22 +481,28 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
         // (wider groups all run the same number of windows: the loop holds barriers)
         for (uint32_t w0 = 0; w0 < most; w0 += RASTER_WINDOW) {
             if (c && cb < w0 + RASTER_WINDOW && cb + c > w0) {
-                const int x0 = box & 255, x1 = (box >> 8) & 255, y0 = (box >> 16) & 255, y1 = (box >> 24) & 255;
-                uint32_t pos = cb;
-                for (int yy = y0; yy <= y1 && pos < w0 + RASTER_WINDOW; ++yy)
-                    for (int xx = x0; xx <= x1 && pos < w0 + RASTER_WINDOW; ++xx, ++pos)
-                        if (pos >= w0) s_cand[grp][pos - w0] = (uint16_t)((t << 8) | (yy * TW + xx));
+                const int y0 = (box >> 16) & 255;
+                for (uint32_t pos = max(cb, w0); pos < min(cb + c, w0 + RASTER_WINDOW); ++pos)
+                    s_cand[grp][pos - w0] = (uint16_t)((t << 8) | (y0 + (int)(pos - cb)));
             }
             group_sync<NW>();
             const uint32_t nf = w0 < total ? min((uint32_t)RASTER_WINDOW, total - w0) : 0u;
             for (uint32_t f = t; f < nf; f += NT) {
                 const uint32_t pr = s_cand[grp][f];
-                const int j = (int)(pr >> 8), pp = (int)(pr & 255u);
-                const int lx = pp % TW, ly = pp / TW;
-                if (lx < vw && ly < vh && covers(s_cov[grp][j], SUB * lx, SUB * ly)) {
-                    atomicAdd(&s_cnt[grp][pp], 1u);
-                    atomicOr(&s_macc[grp][j * NW + (pp >> 6)], 1ull << (pp & 63));
+                const int j = (int)(pr >> 8), ly = (int)(pr & 255u);
+                if (ly >= vh) continue;
+                const CovSetup &cs = s_cov[grp][j];
+                const int x0 = cs.pad0 & 255, x1 = min((cs.pad0 >> 8) & 255, vw - 1);
+                // the row's pixels x0..x1 (a row lies in one 64-bit mask word: TW divides 64)
+                unsigned long long bits = 0ull;
+                for (int lx = x0; lx <= x1; ++lx) {
+                    if (covers(cs, SUB * lx, SUB * ly)) {
+                        const int pp = ly * TW + lx;
+                        atomicAdd(&s_cnt[grp][pp], 1u);
+                        bits |= 1ull << (pp & 63);
+                    }
                 }
+                if (bits) atomicOr(&s_macc[grp][j * NW + ((ly * TW) >> 6)], bits);
             }
             group_sync<NW>();
         }
