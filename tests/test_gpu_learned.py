@@ -267,6 +267,41 @@ def test_resolve_learned_composition(t_sort, K):
     assert torch.allclose(got, ref, rtol=0, atol=2e-6)
 
 
+@pytest.mark.parametrize("layers,kind", [(40, "flat"), (60, "pairs"), (200, "pairs")])
+@pytest.mark.parametrize("K", [3, 5, 8])
+def test_resolve_learned_head_selection_with_equal_depths(layers, kind, K):
+    """The learned resolve finds each pixel's head by selecting the K smallest
+    records without sorting; where equal depths straddle the head's end (layers
+    coinciding in pairs with K odd, or every layer at one depth) the selection
+    must break the tie by triangle id as the sort does.  Its image must equal
+    the composition of the full-sort head (learned_features) with the network's
+    tail (nearly transparent layers: most heads let the tail through; an opaque
+    head adds less than 2^-20 of tail)."""
+    import torch
+    from tests.test_gpu_long_lists import see_through_style, stack
+    m, cam = stack(layers, flat=kind == "flat", pairs=kind == "pairs", seed=K)
+    hot = synth.Hotspot((0.0, 0.0, -1.0), 0.6)
+    st = see_through_style(cam)
+    r = gpu_renderer(m, tuning=(8, 8, 0))
+    counts = r.build(cam, want_counts=True)
+    p = fixed_logit_params(10.0, seed=K)
+    rgba, mask = r.resolve_learned(hot, st, p, K=K, conf_min=0.5)
+    rows = r.learned_features(hot, st, K)
+    y = hx().mlp_forward(cuda(p, torch.float32), rows["feat"])
+    torch.cuda.synchronize()
+    pix = rows["pix"].long()
+    sel = counts.reshape(-1)[pix] > K
+    assert int((rows["head"][sel, 3] < 0.999).sum()) > 0  # heads that let the tail through
+    h = rows["head"][sel]
+    comp = h + (1 - h[:, 3:4]) * y[sel, :4].clamp(0, 1)
+    bg = torch.tensor(list(st.bg) + [0.0], device=comp.device)
+    ref = comp + (1 - comp[:, 3:4]) * bg * torch.tensor([1.0, 1.0, 1.0, 0.0], device=comp.device)
+    got = rgba.reshape(-1, 4)[pix[sel]]
+    d = float((got - ref).abs().max())
+    log(f"[learned] head selection {m.name} K={K}: {int(sel.sum())} pixels, max |d| {d:.2e}")
+    assert d <= 2e-6
+
+
 def test_resolve_learned_errors():
     import torch
     mesh, cams, hots, styles = synth.config0()
