@@ -162,9 +162,12 @@ hexfc_status hexfc_build_fragment_lists(hexfc_ctx *ctx, const hexfc_camera *cam,
 
 /* Resolve the last built lists: sort each pixel's list front to back, shade
  * every fragment (Eq. 1-4) and composite (Section 4.2) over the background.
- * One persistent launch takes the pixels longest list first; lists of any
- * length are sorted (those longer than 2048 fragments in place in the
- * workspace, which leaves each list's records reordered, not changed).
+ * The pixels go by list length to one kernel per length class (a lane, a
+ * wave or a workgroup per list; the classes above 256 fragments on a second
+ * stream, forked and joined with events); each kernel reads its class size
+ * from device memory.  Lists of any length are sorted (those longer than 2048
+ * fragments in place in the workspace, which leaves each list's records
+ * reordered, not changed).
  * rgba_out: device float [height][width][4], premultiplied colour plus
  * accumulated opacity.  Does not wait for the stream.  Errors: ESTATE (no
  * lists), EINVAL (radius <= 0). */
@@ -190,8 +193,7 @@ hexfc_status hexfc_render_frame(hexfc_ctx *ctx, const hexfc_camera *cam, const h
 /* Batch of n views of the same viewport, each with its own camera, hotspot
  * and style, rendered by one captured HIP graph: every stage (transform,
  * binning, count, scan, classes, fill, resolve) runs once over all views, the
- * resolve kernels being persistent grids that read the list classes from
- * device memory.  The first call for a batch shape sizes the buffers
+ * resolve's class kernels reading the list classes from device memory.  The first call for a batch shape sizes the buffers
  * (synchronising `stream` once) and captures the graph; later calls upload
  * the view parameters and launch the graph without synchronising.  The
  * workspace must hold the fragments of all n views.  rgba_out: device float

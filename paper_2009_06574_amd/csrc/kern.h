@@ -21,9 +21,10 @@ constexpr int MAX_PASSES = 64;
 constexpr int MAX_LIST = 2048;                  // longest list the learned and approximate resolves take
 
 // length classes: 0 = short (lane per pixel, n <= t_sort), 1..3 = up to 64,
-// 128, 256 fragments (wave per pixel, bitonic sort in registers), 4..6 = up to
-// 512, 1024, 2048 (workgroup per pixel, bitonic sort in LDS), 7 = longer
-// (workgroup per pixel, sorted in place in the workspace).
+// 128, 256 fragments (wave per pixel, 32-bit keys sorted in registers), 4..6 =
+// up to 512, 1024, 2048 (wave per pixel, 64-bit keys in 8, 16, 32 registers
+// per lane), 7 = longer (workgroup per pixel: sorted in LDS, or in place in
+// the workspace beyond 2048).
 constexpr int NCLASS = 8;
 
 // device-side statistics written by the kernels (zeroed at the start of every
