@@ -352,12 +352,13 @@ __device__ __forceinline__ uint32_t depth_key(const KeySetup &k, int dx, int dy)
 
 // ------------------------------------------------------------------ count / fill
 // One workgroup of 512 lanes per screen tile: S = 512 / (TW*TH) groups of
-// TW*TH lanes (lane = pixel), each group taking one contiguous, equal chunk of
-// the tile's bin, so that the densest tiles are not walked by one wave alone.
-// A group consumes its chunk in batches of TW*TH triangles: each lane sets up
-// one triangle into LDS, then the batch's candidate (triangle, pixel) pairs
-// -- the tile pixels inside each triangle's bounding box -- are tested one
-// per lane.  The count pass also stores, per bin entry and wave, the 64-bit
+// TW*TH lanes (lane = pixel), the tile's bin dealt to the groups in batches of
+// TW*TH entries, round-robin, so that the densest tiles are not walked by one
+// wave alone.  For each of its batches a group's lanes each set up one
+// triangle into LDS, then the batch's candidates -- the rows of the tile
+// inside each triangle's bounding box -- are tested one per lane (the count),
+// or its covered pixels expanded one per lane (the fill).  The count pass
+// also stores, per bin entry and wave, the 64-bit
 // mask of covered pixels, and per group and pixel the fragments of the
 // groups before it; the fill pass expands the masks instead of testing
 // coverage again and places each group's records after those of the groups
@@ -388,19 +389,29 @@ __device__ __forceinline__ void group_sync() {
     }
 }
 
-// chunk [c0, c1) of the tile's bin range [b0, b1) for group grp of S
+// The batches of NT entries that group grp of S takes from the tile's bin
+// range [b0, b1): batch k = [b0 + k NT, b0 + (k + 1) NT) goes to group k % S,
+// so that every batch but the tile's last is full (the per-batch work of a
+// group does not depend on how many of its lanes hold an entry).
 struct Chunk {
-    uint64_t c0, c1;
+    uint64_t b0, b1;
+    int grp;
     int iters;  // batches per group (the same for every group of the workgroup)
 };
 template <int NT, int S>
 __device__ __forceinline__ Chunk bin_chunk(uint64_t b0, uint64_t b1, int grp) {
-    const uint64_t per = (b1 - b0 + S - 1) / S;
+    const uint64_t nb = (b1 - b0 + NT - 1) / NT;
     Chunk c;
-    c.c0 = min(b0 + (uint64_t)grp * per, b1);
-    c.c1 = min(c.c0 + per, b1);
-    c.iters = (int)((per + NT - 1) / NT);
+    c.b0 = b0;
+    c.b1 = b1;
+    c.grp = grp;
+    c.iters = (int)((nb + S - 1) / S);
     return c;
+}
+// first entry of iteration it of the group's batches
+template <int NT, int S>
+__device__ __forceinline__ uint64_t batch_base(const Chunk &c, int it) {
+    return c.b0 + ((uint64_t)it * S + c.grp) * NT;
 }
 
 // Count: every batch of entries is expanded into its candidate (entry, row)
@@ -438,8 +449,8 @@ __global__ void __launch_bounds__(RASTER_WG) k_count(Tiling tl, const uint64_t *
     const Chunk ch = bin_chunk<NT, S>(b0, b1, grp);
     s_cnt[grp][t] = 0;
     for (int it = 0; it < ch.iters; ++it) {
-        const uint64_t base = ch.c0 + (uint64_t)it * NT;
-        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        const uint64_t base = batch_base<NT, S>(ch, it);
+        const int m = base < ch.b1 ? (int)min((uint64_t)NT, ch.b1 - base) : 0;
         uint32_t c = 0;
         int box = 0;
         if (t < m) {
@@ -568,8 +579,8 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, const uint64_t *_
     __syncthreads();
     // expand each batch into fragments, one lane per fragment
     for (int it = 0; it < ch.iters; ++it) {
-        const uint64_t base = ch.c0 + (uint64_t)it * NT;
-        const int m = base < ch.c1 ? (int)min((uint64_t)NT, ch.c1 - base) : 0;
+        const uint64_t base = batch_base<NT, S>(ch, it);
+        const int m = base < ch.b1 ? (int)min((uint64_t)NT, ch.b1 - base) : 0;
         uint32_t c = 0;
         if (t < m) {
 #pragma unroll
