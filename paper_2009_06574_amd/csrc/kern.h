@@ -248,7 +248,7 @@ struct ClassWork {
     uint32_t *queue;  // QUEUE_SEGS * QUEUE_STRIDE u32 of work-queue counters, zero at launch
 };
 constexpr int QUEUE_STRIDE = 32;  // one counter per 128-byte line
-constexpr int QUEUE_SEGS = 8;     // work-queue segments per class (a multiple of the 8 XCDs)
+constexpr int QUEUE_SEGS = 64;    // work-queue counters per class (the most any class kernel uses)
 // Resolve of class c (see NCLASS).  est: the class size when the host knows
 // it (a smaller grid for a short list), else ~0u (a resident grid); the
 // kernel takes the true size from device memory either way.

@@ -571,21 +571,23 @@ __device__ __forceinline__ uint32_t class_size(const ClassWork &w) {
 // without knowing the list's size when the grid is launched).  The list is
 // cut into 8 contiguous parts, one per XCD (workgroups are dealt to the XCDs
 // round-robin, and an XCD's waves share an L2 in which neighbouring pixels
-// find the faces they shade), each part into QUEUE_SEGS / 8 segments with a
-// counter of their own (pops on one address serialise); a wave pops the next
-// item of its home segment, with the next pop in flight while it works on the
-// current one, then helps with what is left of its XCD's other segments and
-// then of the other XCDs'.  `body(item)` is called by the whole wave with a
+// find the faces they shade), each part into SEGS / 8 segments with a
+// counter of their own (pops on one address serialise: the classes that pop
+// one item at a time take more segments); a wave pops the next item of its
+// home segment, with the next pop in flight while it works on the current
+// one, then helps with what is left of its XCD's other segments and then of
+// the other XCDs'.  `body(item)` is called by the whole wave with a
 // wave-uniform item.
-template <int PER_POP, class Body>
+template <int PER_POP, int SEGS, class Body>
 __device__ __forceinline__ void drain(uint32_t total, uint32_t *__restrict__ queue, int lane, Body &&body) {
-    constexpr int SUB = QUEUE_SEGS / 8;
+    static_assert(SEGS % 8 == 0 && SEGS <= QUEUE_SEGS, "queue segments");
+    constexpr int SUB = SEGS / 8;
     const int xcd = blockIdx.x & 7, sub = (blockIdx.x >> 3) % SUB;
 #pragma unroll 1
-    for (int h = 0; h < QUEUE_SEGS; ++h) {
+    for (int h = 0; h < SEGS; ++h) {
         const int x = ((xcd + h / SUB) & 7) * SUB + (sub + h) % SUB;
-        const uint32_t lo = (uint32_t)((uint64_t)total * x / QUEUE_SEGS),
-                       hi = (uint32_t)((uint64_t)total * (x + 1) / QUEUE_SEGS);
+        const uint32_t lo = (uint32_t)((uint64_t)total * x / SEGS),
+                       hi = (uint32_t)((uint64_t)total * (x + 1) / SEGS);
         uint32_t *ctr = queue + x * QUEUE_STRIDE;
         if (lo == hi || (h && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo))
             continue;  // (an empty segment, or one already taken)
@@ -634,7 +636,7 @@ __device__ __forceinline__ void resolve_waves(const ClassWork &w, const ResolveA
     if (!total) return;
     const uint64_t base = rec_base(a);
     // (short lists take several items per pop: their work would not hide its latency)
-    drain<R == 1 ? 4 : R == 2 ? 2 : 1>(total, w.queue, lane, [&](uint32_t item) {
+    drain<R == 1 ? 4 : R == 2 ? 2 : 1, R == 4 ? 64 : 8>(total, w.queue, lane, [&](uint32_t item) {
         const uint32_t p = w.list[item];
         if (p != PIX_SKIP) resolve_wave<R>(a, base, p, lane, stash[wave]);
     });
