@@ -81,6 +81,7 @@ struct hexfc_ctx {
     hexfc::DevBuf count_rm_tmp;
     // learned tail: per-row head, features and pixel ids, fallback lists
     hexfc::DevBuf l_head, l_feat, l_pix, l_fb;
+    hexfc::DevBuf frange;  // int4 [views x faces]: both triangles' tile ranges (binning)
     // device address of this GPU's static scratch (allocation-free learned
     // resolve), looked up once per device; nullptr with the reason when the
     // lookup failed

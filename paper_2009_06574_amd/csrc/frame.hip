@@ -120,6 +120,7 @@ hexfc_status ensure_frame_buffers(hexfc_ctx *ctx, int nv, const Tiling &tl) {
         FAIL(ctx, HEXFC_ERANGE, "%lld padded pixels in the batch exceed 2^31", (long long)np);
     TRY(grow(ctx, ctx->vscr, sizeof(int4) * ctx->V * nv));
     TRY(grow(ctx, ctx->fscr, sizeof(int4) * 4 * std::max<int64_t>(ctx->F, 1) * nv));
+    TRY(grow(ctx, ctx->frange, sizeof(int4) * std::max<int64_t>(ctx->F, 1) * nv));
     TRY(grow(ctx, ctx->bslot, sizeof(uint32_t) * 4 * std::max<int64_t>(ctx->F, 1) * nv));
     if (nv > 1) {
         const void *old = ctx->vert_b.p;
@@ -192,13 +193,14 @@ void enqueue_front(hexfc_ctx *ctx, int nv, const Tiling &tl, hipStream_t s, Fron
     {
         ScopedTimer tm(ctx, s, KID_BIN_COUNT);
         launch_tri_bin_count(fc, ctx->face_ord.as<uint32_t>(), ctx->F, nv, vscr, ctx->V, tl,
-                             ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(), ctx->bslot.as<uint32_t>(), s);
+                             ctx->tile_cnt.as<uint32_t>(), ctx->fscr.as<int4>(), ctx->bslot.as<uint32_t>(),
+                             ctx->frange.as<int4>(), s);
         launch_scan_u32_u64(ctx->tile_cnt.as<uint32_t>() + nt, nt, ctx->tile_off.as<uint64_t>(),
                             ctx->scan_tmp.as<uint64_t>(), stats + ST_BINS, s);
     }
     {
         ScopedTimer tm(ctx, s, KID_BIN_SCATTER);
-        launch_tri_bin_scatter(ctx->fscr.as<int4>(), ctx->F, nv, tl, ctx->tile_off.as<uint64_t>(),
+        launch_tri_bin_scatter(ctx->frange.as<int4>(), ctx->F, nv, tl, ctx->tile_off.as<uint64_t>(),
                                ctx->tile_cnt.as<uint32_t>(), ctx->tile_fill.as<uint32_t>(), ctx->bins.as<uint32_t>(),
                                ctx->bin_cap, ctx->bslot.as<uint32_t>(), s);
     }

@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
                                                  uint32_t *__restrict__ tile_ctr, const uint64_t *__restrict__ tile_off,
                                                  uint32_t *__restrict__ bins, uint64_t cap,
                                                  int4 *__restrict__ fscr, uint32_t *__restrict__ bslot,
-                                                 const uint32_t *__restrict__ tile_lo, int64_t NT) {
+                                                 const uint32_t *__restrict__ tile_lo, int64_t NT,
+                                                 int4 *__restrict__ frange) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (view, position in binning order)
     const int64_t view = i < NVF ? i / F : 0, fo = i - view * F;
     // bin entries name triangles by binning position (2 fo + t): the count and
@@ -119,16 +120,24 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
     const int64_t f = fo;
     int r0[4] = {0, -1, 0, -1}, r1[4] = {0, -1, 0, -1};  // tile ranges of triangles 0 and 1: x0, x1, y0, y1
     bool ok0 = false, ok1 = false;
-    if (i < NVF) {
+    if (SCATTER && i < NVF) {
+        // the count pass stored both triangles' tile ranges (16 B instead of
+        // the 64 B of screen vertices they come from)
+        const int4 rg = frange[i];
+        ok0 = rg.x != -1;
+        ok1 = rg.z != -1;
+        r0[0] = rg.x & 0xffff;
+        r0[1] = (int)((uint32_t)rg.x >> 16);
+        r0[2] = rg.y & 0xffff;
+        r0[3] = (int)((uint32_t)rg.y >> 16);
+        r1[0] = rg.z & 0xffff;
+        r1[1] = (int)((uint32_t)rg.z >> 16);
+        r1[2] = rg.w & 0xffff;
+        r1[3] = (int)((uint32_t)rg.w >> 16);
+    } else if (i < NVF) {
         int4 p0, p1, p2, p3;
         int4 *fs = fscr + 4 * i;  // (view, binning position) record of the four screen vertices
-        if (SCATTER) {  // the count pass stored them
-            p0 = fs[0];
-            p0.w = p0.w < 0;
-            p1 = fs[1];
-            p2 = fs[2];
-            p3 = fs[3];
-        } else {
+        {
             const int4 c = face_c[fo];
             const int4 *vs = vscr + view * V;
             p0 = vs[c.x];
@@ -143,6 +152,8 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
         }
         ok0 = tri_tile_range(p0, p1, p2, tl, r0[0], r0[1], r0[2], r0[3]);
         ok1 = tri_tile_range(p0, p2, p3, tl, r1[0], r1[1], r1[2], r1[3]);
+        frange[i] = make_int4(ok0 ? r0[0] | (r0[1] << 16) : -1, ok0 ? r0[2] | (r0[3] << 16) : 0,
+                              ok1 ? r1[0] | (r1[1] << 16) : -1, ok1 ? r1[2] | (r1[3] << 16) : 0);
     }
     const int64_t tile0 = view * tl.ntiles;
     // union of the two ranges; a tile of it takes the face's triangles that overlap it
@@ -960,23 +971,23 @@ __global__ void k_tile_totals(uint32_t *__restrict__ ctr, int64_t NT) {
 
 void launch_tri_bin_count(const int4 *face_c, const uint32_t *face_ord, int64_t F, int nv, const int4 *vscr,
                           int64_t V, const Tiling &tl, uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot,
-                          hipStream_t s) {
+                          int4 *frange, hipStream_t s) {
     const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
         k_tri_bin<false><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(face_c, face_ord, F, n, vscr, V, tl,
                                                                           tile_cnt,
                                                                           nullptr, nullptr, 0, fscr, bslot, nullptr,
-                                                                          NT);
+                                                                          NT, frange);
     if (NT > 0) k_tile_totals<<<dim3((unsigned)((NT + 255) / 256)), 256, 0, s>>>(tile_cnt, NT);
 }
-void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
+void launch_tri_bin_scatter(const int4 *frange, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
                             const uint32_t *tile_lo, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             const uint32_t *bslot, hipStream_t s) {
     const int64_t n = F * nv, NT = (int64_t)tl.ntiles * nv;
     if (n > 0)
         k_tri_bin<true><<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(
-            nullptr, nullptr, F, n, nullptr, 0, tl, tile_fill, tile_off, bins, bin_cap, const_cast<int4 *>(fscr),
-            const_cast<uint32_t *>(bslot), tile_lo, NT);
+            nullptr, nullptr, F, n, nullptr, 0, tl, tile_fill, tile_off, bins, bin_cap, nullptr,
+            const_cast<uint32_t *>(bslot), tile_lo, NT, const_cast<int4 *>(frange));
 }
 
 #define HEXFC_TILE_DISPATCH(TWv, THv, CALL) \

@@ -176,10 +176,13 @@ void launch_transform(const int4 *posq, int64_t V, int nv, const ViewParams *vie
 // face_c / face_ord: the faces' corner ids and canonical ids in binning order.
 // Bin entries and fscr are indexed by binning position (entry = 2 position +
 // triangle); the fill writes records with canonical triangle ids.
+// frange: per (view, binning position) the two triangles' tile ranges
+// (x0 | x1 << 16, y0 | y1 << 16 each; x = -1: culled), written by the
+// counting pass and read by the scatter pass.
 void launch_tri_bin_count(const int4 *face_c, const uint32_t *face_ord, int64_t F, int nv, const int4 *vscr,
                           int64_t V, const Tiling &tl, uint32_t *tile_cnt, int4 *fscr, uint32_t *bslot,
-                          hipStream_t s);
-void launch_tri_bin_scatter(const int4 *fscr, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
+                          int4 *frange, hipStream_t s);
+void launch_tri_bin_scatter(const int4 *frange, int64_t F, int nv, const Tiling &tl, const uint64_t *tile_off,
                             const uint32_t *tile_lo, uint32_t *tile_fill, uint32_t *bins, uint64_t bin_cap,
                             const uint32_t *bslot, hipStream_t s);
 // Count and fill run 512-lane workgroups per tile.  masks: per bin entry and
