@@ -20,19 +20,64 @@ namespace hexfc {
 
 // Sort key order: record = (depth field << 32) | triangle id, ascending.
 
+// x as held by lane ^ m, for m a power of two below 64 (a constant once the
+// callers' loops are unrolled), without the LDS round trip of a general lane
+// permutation where the hardware has a fixed one: quad permutations (m = 1,
+// 2) and the rotation of a 16-lane row by 8 (m = 8) as DPP operand
+// modifiers, gfx950's swaps of 16-lane row pairs (m = 16) and of wave halves
+// (m = 32), and the swizzle of the LDS crossbar for m = 4.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, int m, int lane) {
+    switch (m) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1f | (4 << 10));               // and 31, xor 4
+    case 8: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);  // row_ror 8
+    case 16: {
+        // rows 1, 3 of the first operand trade places with rows 0, 2 of the second
+        const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16) ? s[0] : s[1];
+    }
+    default: {
+        // lanes 32..63 of the first operand trade places with lanes 0..31 of the second
+        const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32) ? s[0] : s[1];
+    }
+    }
+}
+__device__ __forceinline__ uint64_t xor_lane(uint64_t x, int m, int lane) {
+    return ((uint64_t)xor_lane((uint32_t)(x >> 32), m, lane) << 32) | xor_lane((uint32_t)x, m, lane);
+}
+__device__ __forceinline__ float xor_lane(float x, int m, int lane) {
+    return __uint_as_float(xor_lane(__float_as_uint(x), m, lane));
+}
+__device__ __forceinline__ float lane0(float x) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(x), 0));
+}
+
 struct Frag {
     float r, g, b, a;
 };
 
-__device__ __forceinline__ float segdist(float px, float py, float pz, float ax, float ay, float az, float bx, float by,
-                                         float bz) {
+// Squared distance from p to the segment a-b (the shading compares distances
+// with thresholds and with each other only, so their squares serve).
+__device__ __forceinline__ float segdist2(float px, float py, float pz, float ax, float ay, float az, float bx,
+                                          float by, float bz) {
     float ux = bx - ax, uy = by - ay, uz = bz - az;
     float wx = px - ax, wy = py - ay, wz = pz - az;
     float l2 = ux * ux + uy * uy + uz * uz;
     float t = l2 > 0.f ? (wx * ux + wy * uy + wz * uz) * __builtin_amdgcn_rcpf(l2) : 0.f;
     t = fminf(fmaxf(t, 0.f), 1.f);
     float dx = wx - t * ux, dy = wy - t * uy, dz = wz - t * uz;
-    return sqrtf(dx * dx + dy * dy + dz * dz);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// a b - c d for integers a, b, c, d below 2^19 in magnitude (exact in FP32),
+// to within 2 ulp: the rounding error of c d is recovered with an FMA
+// (Kahan's 2 x 2 determinant).
+__device__ __forceinline__ float det2(float a, float b, float c, float d) {
+    const float w = c * d;
+    const float e = fmaf(-c, d, w);
+    return fmaf(a, b, -w) + e;
 }
 
 // Premultiplied colour and opacity of one fragment: triangle `tri` at pixel
@@ -47,13 +92,16 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
     // the triangle's screen vertices: corners 0, 1 + t, 2 + t
     const int4 s0 = vert[c.x].scr, s1 = vert[t1 ? c.z : c.y].scr, s2 = vert[t1 ? c.w : c.z].scr;
     // perspective-correct barycentrics: weight of vertex i = E_opp(i) * q_i,
-    // the edge functions exact in integers (each factor below 2^18), the
+    // the edge functions from integer screen coordinates (below 2^18 in
+    // magnitude: every difference is exact in FP32) to within 2 ulp, the
     // weights in FP32 (positive inside the triangle: no cancellation)
-    const int X = SUB * x + SUB / 2, Y = SUB * y + SUB / 2;
-    const long long e0 = (long long)(s2.x - s1.x) * (Y - s1.y) - (long long)(s2.y - s1.y) * (X - s1.x);
-    const long long e1 = (long long)(s0.x - s2.x) * (Y - s2.y) - (long long)(s0.y - s2.y) * (X - s2.x);
-    const long long e2 = (long long)(s1.x - s0.x) * (Y - s0.y) - (long long)(s1.y - s0.y) * (X - s0.x);
-    const float w0 = (float)e0 * (float)s0.z, w1 = (float)e1 * (float)s1.z, w2 = (float)e2 * (float)s2.z;
+    const float X = (float)(SUB * x + SUB / 2), Y = (float)(SUB * y + SUB / 2);
+    const float x0 = (float)s0.x, y0 = (float)s0.y, x1 = (float)s1.x, y1 = (float)s1.y;
+    const float x2 = (float)s2.x, y2 = (float)s2.y;
+    const float e0 = det2(x2 - x1, Y - y1, y2 - y1, X - x1);
+    const float e1 = det2(x0 - x2, Y - y2, y0 - y2, X - x2);
+    const float e2 = det2(x1 - x0, Y - y0, y1 - y0, X - x0);
+    const float w0 = e0 * (float)s0.z, w1 = e1 * (float)s1.z, w2 = e2 * (float)s2.z;
     const float inv = __builtin_amdgcn_rcpf(w0 + w1 + w2);
     const float l0 = w0 * inv, l1 = w1 * inv, l2 = w2 * inv;
     // corners relative to corner 0 (exact: all are multiples of 2^-16)
@@ -71,19 +119,19 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
     float dist;
     if (sp.lens_mode == 1) {
         const float ex = ((float)x + 0.5f) - sp.hc[0], ey = ((float)y + 0.5f) - sp.hc[1];
-        dist = sqrtf(ex * ex + ey * ey) * sp.inv_r;
+        dist = __builtin_amdgcn_sqrtf(ex * ex + ey * ey) * sp.inv_r;
     } else {
         const float hx = (P0.x - sp.hc[0]) + px, hy = (P0.y - sp.hc[1]) + py, hz = (P0.z - sp.hc[2]) + pz;
-        dist = sqrtf(hx * hx + hy * hy + hz * hz) * sp.inv_r;
+        dist = __builtin_amdgcn_sqrtf(hx * hx + hy * hy + hz * hz) * sp.inv_r;
     }
     float u = fminf(fmaxf((dist - 0.7f) * (1.0f / 0.3f), 0.f), 1.f);
     const float focus = 1.f - u * u * (3.f - 2.f * u);
-    // distances to the four face edges
+    // squared distances to the four face edges
     float d[4];
-    d[0] = segdist(px, py, pz, 0.f, 0.f, 0.f, r1x, r1y, r1z);
-    d[1] = segdist(px, py, pz, r1x, r1y, r1z, r2x, r2y, r2z);
-    d[2] = segdist(px, py, pz, r2x, r2y, r2z, r3x, r3y, r3z);
-    d[3] = segdist(px, py, pz, r3x, r3y, r3z, 0.f, 0.f, 0.f);
+    d[0] = segdist2(px, py, pz, 0.f, 0.f, 0.f, r1x, r1y, r1z);
+    d[1] = segdist2(px, py, pz, r1x, r1y, r1z, r2x, r2y, r2z);
+    d[2] = segdist2(px, py, pz, r2x, r2y, r2z, r3x, r3y, r3z);
+    d[3] = segdist2(px, py, pz, r3x, r3y, r3z, 0.f, 0.f, 0.f);
     const uint32_t lv = F.lvl;
     const float4 te4 = F.te;
     const float te[4] = {te4.x, te4.y, te4.z, te4.w};
@@ -97,16 +145,18 @@ __device__ __forceinline__ Frag shade(const DevMesh &m, const VertRec *__restric
         if (inC && d[k] < dC) { dC = d[k]; tC = te[k]; }
         dA = fminf(dA, d[k]);
     }
-    const float w = (1.f + sp.k_focus * focus) * sp.w_base;
-    const bool eF = dF <= w, eC = dC <= w;
-    const bool h = !eF && dF <= w + sp.halo_w * focus;
+    // (distances squared: thresholds squared)
+    const float w = (1.f + sp.k_focus * focus) * sp.w_base, wh = w + sp.halo_w * focus;
+    const bool eF = dF <= w * w, eC = dC <= w * w;
+    const bool h = !eF && dF <= wh * wh;
     const float dk = 1.f - sp.darken * focus;
     const float AF = eF ? 1.f : (h ? sp.halo_a : 0.f);
     const float fe = eC ? 1.f - focus : 0.f;  // (1 - focus) * e_C
     float Ce[3];
     Frag o;
     const float ae = fe + focus * AF;
-    const bool acc = dA <= (2.f / 3.f) * sp.w_base;
+    const float wa = (2.f / 3.f) * sp.w_base;
+    const bool acc = dA <= wa * wa;
     const float se = acc ? sp.s : 1.f;
     const float ahat = sp.a_lo + (sp.a_hi - sp.a_lo) * tf;
     const float dc = fminf(dist, 1.f);
@@ -219,7 +269,7 @@ __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
                 const bool lower = (lane & lm) == 0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const K o = __shfl_xor(v[r], lm);
+                    const K o = xor_lane(v[r], lm, lane);
                     const bool up = ((lane * R + r) & k) == 0;
                     v[r] = (lower == up) ? (v[r] < o ? v[r] : o) : (v[r] < o ? o : v[r]);
                 }
@@ -246,7 +296,9 @@ __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
 __device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, float &A, int lane) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const float q0 = __shfl_down(C0, o), q1 = __shfl_down(C1, o), q2 = __shfl_down(C2, o), qa = __shfl_down(A, o);
+        // (the lanes that combine, lane % 2o == 0, read lane + o = lane ^ o)
+        const float q0 = xor_lane(C0, o, lane), q1 = xor_lane(C1, o, lane), q2 = xor_lane(C2, o, lane),
+                    qa = xor_lane(A, o, lane);
         if ((lane & (2 * o - 1)) == 0) {
             const float T = 1.f - A;
             C0 += T * q0;
@@ -285,10 +337,10 @@ __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRe
             ca = fr.a;
         }
         over_reduce(c0, c1, c2, ca, lane);
-        c0 = __shfl(c0, 0);
-        c1 = __shfl(c1, 0);
-        c2 = __shfl(c2, 0);
-        ca = __shfl(ca, 0);
+        c0 = lane0(c0);
+        c1 = lane0(c1);
+        c2 = lane0(c2);
+        ca = lane0(ca);
         const float T = 1.f - A;
         C0 += T * c0;
         C1 += T * c1;
@@ -737,8 +789,9 @@ void launch_resolve_class(int c, const ClassWork &w, uint32_t est, int t_sort, c
 enum { TAIL_FEATURES = 0, TAIL_TRAIN = 1, TAIL_RESOLVE = 2 };
 
 __device__ __forceinline__ float wave_sum(float v) {
+    const int lane = (int)__lane_id();
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    for (int o = 32; o > 0; o >>= 1) v += xor_lane(v, o, lane);
     return v;
 }
 
@@ -826,7 +879,7 @@ __device__ __forceinline__ float4 head_composite(const ResolveArgs &a, const Pix
         HA = fr.a;
     }
     over_reduce(H0, H1, H2, HA, lane);
-    return make_float4(__shfl(H0, 0), __shfl(H1, 0), __shfl(H2, 0), __shfl(HA, 0));
+    return make_float4(lane0(H0), lane0(H1), lane0(H2), lane0(HA));
 }
 
 template <int R, int MODE>
