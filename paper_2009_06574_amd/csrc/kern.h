@@ -111,6 +111,16 @@ struct ViewParams {
     float pad0, pad1;
 };
 
+// A view's parameters, read through the constant address space: the view
+// table does not change while a kernel runs, so uniform reads of it become
+// scalar loads, and repeated reads need not be repeated (a vector load and a
+// wait per use otherwise: the compiler cannot tell that the kernel's stores
+// leave the table alone).
+typedef const __attribute__((address_space(4))) ViewParams ConstViewParams;
+__device__ __forceinline__ const ViewParams &view_params(const ViewParams *views, int64_t v) {
+    return *(const ViewParams *)&((ConstViewParams *)views)[v];
+}
+
 struct Tiling {
     int W, H, TW, TH, ntx, nty, ntiles;
 };

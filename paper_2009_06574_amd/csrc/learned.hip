@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(256) k_mlp_apply(const float *__restrict__ par
         const float T = 1.f - h.w;
         const float C0 = h.x + T * tail.x, C1 = h.y + T * tail.y, C2 = h.z + T * tail.z, A = h.w + T * tail.w;
         const float Tb = 1.f - A;
-        const ShadeParams &sp = a.views[pr.view].sp;
+        const ShadeParams &sp = view_params(a.views, pr.view).sp;
         reinterpret_cast<float4 *>(a.rgba)[o] =
             make_float4(C0 + Tb * sp.bg[0], C1 + Tb * sp.bg[1], C2 + Tb * sp.bg[2], A);
     }

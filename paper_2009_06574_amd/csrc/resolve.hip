@@ -240,7 +240,7 @@ __device__ __forceinline__ void resolve_lane(const ResolveArgs &a, uint64_t base
         for (uint32_t i = 0; i < n; ++i) dst[i] = col[i][lane];
     }
     if (a.rgba) {
-        const ShadeParams &sp = a.views[pr.view].sp;
+        const ShadeParams &sp = view_params(a.views, pr.view).sp;
         const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
         float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
         for (uint32_t i = 0; i < n; ++i) {
@@ -318,7 +318,7 @@ __device__ __forceinline__ void over_reduce(float &C0, float &C1, float &C2, flo
 template <int R, class TriOf>
 __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRef &pr, uint32_t n, int lane,
                                              uint32_t ordered, TriOf &&tri_of) {
-    const ShadeParams &sp = a.views[pr.view].sp;
+    const ShadeParams &sp = view_params(a.views, pr.view).sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;  // blended rounds (uniform over the wave)
     constexpr int UNROLL = R <= 8 ? R : 1;
@@ -365,10 +365,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the wave) for the shading rounds, so that they hold no registers across
 // the shading; longer lists keep them in registers.
 template <int R>
-__device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint64_t base, uint32_t p, int lane,
+__device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint32_t p, uint32_t cnt, uint64_t first, int lane,
                                              uint32_t *__restrict__ stash) {
-    uint32_t n = min(a.count[p], (uint32_t)(64 * R));  // the class guarantees n <= 64 R
-    const uint64_t first = a.off[p] - base;
+    uint32_t n = min(cnt, (uint32_t)(64 * R));  // the class guarantees n <= 64 R
     if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
     const uint64_t *src = a.rec + first;
     const PixelRef pr = pixel_ref(a.tl, p);
@@ -581,7 +580,7 @@ __device__ void resolve_block(const ResolveArgs &a, uint64_t base, uint32_t p, B
     }
     if (a.rgba) {
         const int lane = tid & 63, wave = tid >> 6;
-        const ShadeParams &sp = a.views[pr.view].sp;
+        const ShadeParams &sp = view_params(a.views, pr.view).sp;
         const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
         float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;  // uniform over the workgroup
         for (uint32_t r0 = 0; r0 < n; r0 += RT) {
@@ -679,7 +678,7 @@ __global__ void __launch_bounds__(64) k_resolve_short(ClassWork w, ResolveArgs a
 }
 
 // Wave-per-pixel lists (classes 1..6).  Up to 8 keys per lane the kernel is
-// held to 96 VGPRs (5 waves per SIMD).
+// held to a register budget that keeps WAVES_R waves per SIMD resident.
 template <int R>
 __device__ __forceinline__ void resolve_waves(const ClassWork &w, const ResolveArgs &a) {
     __shared__ uint32_t stash[RT / 64][R <= 4 ? 512 : 1];
@@ -690,12 +689,14 @@ __device__ __forceinline__ void resolve_waves(const ClassWork &w, const ResolveA
     // (short lists take several items per pop: their work would not hide its latency)
     drain<R == 1 ? 4 : R == 2 ? 2 : 1, R == 4 ? 64 : 8>(total, w.queue, lane, [&](uint32_t item) {
         const uint32_t p = w.list[item];
-        if (p != PIX_SKIP) resolve_wave<R>(a, base, p, lane, stash[wave]);
+        if (p != PIX_SKIP) resolve_wave<R>(a, p, a.count[p], a.off[p] - base, lane, stash[wave]);
     });
 }
 template <int R>
-__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(5, 8))) k_resolve_wave(ClassWork w,
-                                                                                              ResolveArgs a) {
+constexpr int WAVES_R = R <= 2 ? 7 : R == 4 ? 6 : 5;
+template <int R>
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(WAVES_R<R>, 8))) k_resolve_wave(ClassWork w,
+                                                                                                        ResolveArgs a) {
     resolve_waves<R>(w, a);
 }
 template <int R>
@@ -718,20 +719,25 @@ __global__ void __launch_bounds__(RT) k_resolve_block(ClassWork w, ResolveArgs a
 
 // Workgroups of each class kernel the device holds at once (the grid is never
 // smaller: a low estimate then costs the balance of a persistent grid, not
-// a few workgroups striding over a long list).
+// a few workgroups striding over a long list), at most `cap` per CU: the
+// wave-per-pixel kernels' workgroups hold one wave per SIMD each, and more
+// resident waves than a class needs to hide its latency only compete for the
+// caches and leave less room to the long classes on the second stream
+// (measured best: 5 waves per SIMD for classes 1 and 2, 6 for class 3; their
+// registers would allow 7).
 template <class K>
-static int resident(int device, K kernel, int threads) {
+static int resident(int device, K kernel, int threads, int cap = 1 << 20) {
     int cus = 0, per = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
-    return std::max(1, cus) * std::max(1, per);
+    return std::max(1, cus) * std::max(1, std::min(per, cap));
 }
 
 void resolve_min_grids(int device, int out[NCLASS + 2]) {
     out[0] = resident(device, k_resolve_short<16>, 64);
-    out[1] = resident(device, k_resolve_wave<1>, RT);
-    out[2] = resident(device, k_resolve_wave<2>, RT);
-    out[3] = resident(device, k_resolve_wave<4>, RT);
+    out[1] = resident(device, k_resolve_wave<1>, RT, 5);
+    out[2] = resident(device, k_resolve_wave<2>, RT, 5);
+    out[3] = resident(device, k_resolve_wave<4>, RT, 6);
     out[4] = resident(device, k_resolve_wave<8>, RT);
     out[5] = resident(device, k_resolve_wave_wide<16>, RT);
     out[6] = resident(device, k_resolve_wave_wide<32>, RT);
@@ -871,7 +877,7 @@ __device__ __forceinline__ float4 head_composite(const ResolveArgs &a, const Pix
                                                  int lane) {
     float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
     if ((uint32_t)lane < m) {
-        const ViewParams &vp = a.views[pr.view];
+        const ViewParams &vp = view_params(a.views, pr.view);
         const Frag fr = shade(a.mesh, a.mesh.vert + pr.view * a.mesh.V, vp.sp, (uint32_t)(h & 0xffffffffu), pr.x, pr.y);
         H0 = fr.r;
         H1 = fr.g;
@@ -904,7 +910,7 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         v[r] = e < n ? src[e] : ~0ull;
     }
     const PixelRef pr = pixel_ref(a.tl, p);
-    const ViewParams &vp = a.views[pr.view];
+    const ViewParams &vp = view_params(a.views, pr.view);
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     const int64_t o = out_base + wave;
@@ -1027,7 +1033,7 @@ __global__ void __launch_bounds__(256) k_boundary_depth(Tiling tl, const uint64_
     const int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= p1) return;
     const int64_t view = p / ((int64_t)tl.ntiles * TPX);
-    if (!(views[view].sp.sil_a > 0.f)) return;
+    if (!(view_params(views, view).sp.sil_a > 0.f)) return;
     uint32_t n = count[p];
     const uint64_t first = off[p] - off[p0];
     if (first + n > rec_cap) n = 0;
@@ -1045,7 +1051,7 @@ __global__ void __launch_bounds__(256) k_silhouette(Tiling tl, int64_t npx, cons
     if (i >= npx) return;
     const int64_t WH = (int64_t)tl.W * tl.H;
     const int64_t view = i / WH;
-    const ShadeParams &sp = views[view].sp;
+    const ShadeParams &sp = view_params(views, view).sp;
     const float a = sp.sil_a;
     if (!(a > 0.f)) return;
     const int x = (int)((i - view * WH) % tl.W), y = (int)((i - view * WH) / tl.W);
@@ -1186,7 +1192,7 @@ __global__ void __launch_bounds__(256) k_mlab_shade(const uint32_t *__restrict__
     for (int r = 0; r < R; ++r) v[r] = (v[r] << 32) | (v[r] >> 32);  // triangle id first: primitive order
     bitonic_sort<R>(v, lane);
     const PixelRef pr = pixel_ref(a.tl, p);
-    const ShadeParams &sp = a.views[pr.view].sp;
+    const ShadeParams &sp = view_params(a.views, pr.view).sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     const uint64_t first = a.off[p] - rec_base(a);
 #pragma unroll
@@ -1270,7 +1276,7 @@ __global__ void __launch_bounds__(256) k_mlab_blend(const uint32_t *__restrict__
     for (uint32_t e = 0; e < n; ++e) nd.insert(mc[first + e], mz[first + e], k);
     const PixelRef pr = pixel_ref(a.tl, p);
     reinterpret_cast<float4 *>(a.rgba)[(pr.view * a.tl.H + pr.y) * (int64_t)a.tl.W + pr.x] =
-        nd.finish(a.views[pr.view].sp);
+        nd.finish(view_params(a.views, pr.view).sp);
 }
 
 // Short lists (at most TS fragments): one lane per pixel sorts its list by
@@ -1297,7 +1303,7 @@ __global__ void __launch_bounds__(64) k_mlab_short(const uint32_t *__restrict__ 
         col[j][lane] = r;
     }
     const PixelRef pr = pixel_ref(a.tl, p);
-    const ShadeParams &sp = a.views[pr.view].sp;
+    const ShadeParams &sp = view_params(a.views, pr.view).sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     MlabNodes nd;
     for (uint32_t i = 0; i < n; ++i) {
@@ -1319,7 +1325,7 @@ __global__ void __launch_bounds__(256) k_resolve_moments(const uint32_t *__restr
     uint64_t v[R];
     const uint32_t n = load_list<R>(a, p, lane, v);
     const PixelRef pr = pixel_ref(a.tl, p);
-    const ViewParams &vp = a.views[pr.view];
+    const ViewParams &vp = view_params(a.views, pr.view);
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     const double zs = 1.0 / ((double)vp.w1 - (double)vp.w0);
@@ -1396,7 +1402,7 @@ __global__ void __launch_bounds__(256) k_moments_short(const uint32_t *__restric
     if (first + n > a.rec_cap) n = 0;
     const uint64_t *src = a.rec + first;
     const PixelRef pr = pixel_ref(a.tl, p);
-    const ViewParams &vp = a.views[pr.view];
+    const ViewParams &vp = view_params(a.views, pr.view);
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
     const double zs = 1.0 / ((double)vp.w1 - (double)vp.w0);
