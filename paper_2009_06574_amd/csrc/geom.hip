@@ -64,25 +64,29 @@ __device__ __forceinline__ void tri_ids(const int4 c, int t, int &a, int &b, int
 // triangle is culled (flagged vertex, zero snapped area, nothing on screen).
 __device__ __forceinline__ bool tri_tile_range(const int4 a, const int4 b, const int4 d, const Tiling &tl, int &tx0,
                                                int &tx1, int &ty0, int &ty1) {
+    static_assert(SUB == 16, "sub-pixel shifts");
     if (a.w | b.w | d.w) return false;
     long long area = (long long)(b.x - a.x) * (d.y - a.y) - (long long)(b.y - a.y) * (d.x - a.x);
     if (area == 0) return false;
     int xmin = min(a.x, min(b.x, d.x)), xmax = max(a.x, max(b.x, d.x));
     int ymin = min(a.y, min(b.y, d.y)), ymax = max(a.y, max(b.y, d.y));
-    // pixel i is a candidate iff xmin <= 16 i + 8 <= xmax
-    int i0 = (int)(-floordiv_pos(-(long long)(xmin - 8), SUB));
-    int i1 = (int)floordiv_pos((long long)(xmax - 8), SUB);
-    int j0 = (int)(-floordiv_pos(-(long long)(ymin - 8), SUB));
-    int j1 = (int)floordiv_pos((long long)(ymax - 8), SUB);
+    // pixel i is a candidate iff xmin <= 16 i + 8 <= xmax: i from
+    // ceil((xmin - 8) / 16) to floor((xmax - 8) / 16) (arithmetic shifts floor)
+    int i0 = -((8 - xmin) >> 4);
+    int i1 = (xmax - 8) >> 4;
+    int j0 = -((8 - ymin) >> 4);
+    int j1 = (ymax - 8) >> 4;
     i0 = max(i0, 0);
     j0 = max(j0, 0);
     i1 = min(i1, tl.W - 1);
     j1 = min(j1, tl.H - 1);
     if (i0 > i1 || j0 > j1) return false;
-    tx0 = i0 / tl.TW;
-    tx1 = i1 / tl.TW;
-    ty0 = j0 / tl.TH;
-    ty1 = j1 / tl.TH;
+    // (tile sides are powers of two)
+    const int sx = __builtin_ctz((unsigned)tl.TW), sy = __builtin_ctz((unsigned)tl.TH);
+    tx0 = i0 >> sx;
+    tx1 = i1 >> sx;
+    ty0 = j0 >> sy;
+    ty1 = j1 >> sy;
     return true;
 }
 
@@ -113,7 +117,11 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
                                                  const uint32_t *__restrict__ tile_lo, int64_t NT,
                                                  int4 *__restrict__ frange) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (view, position in binning order)
-    const int64_t view = i < NVF ? i / F : 0, fo = i - view * F;
+    // (view = i / F: none for one view, in 32 bits while the views' faces count below 2^32)
+    const int64_t view = (NVF <= F || i >= NVF) ? 0
+                         : NVF <= 0xffffffffll ? (int64_t)((uint32_t)i / (uint32_t)F)
+                                               : i / F;
+    const int64_t fo = i - view * F;
     // bin entries name triangles by binning position (2 fo + t): the count and
     // fill passes then read the screen vertices in binning order too; the fill
     // takes the canonical face id for the records from the w of corner 0
@@ -168,11 +176,16 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
     const int n = (ok0 || ok1) ? nx * (u[3] - u[2] + 1) : 0;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int kx = -1, ky = 0;  // tile k of the range, row-major: (u[0] + kx, u[2] + ky)
     for (int k = 0; __any(k < n); ++k) {
+        if (++kx >= nx) {
+            kx = 0;
+            ++ky;
+        }
         int64_t tile = -1;
         bool h0 = false, h1 = false;
         if (k < n) {
-            const int x = u[0] + k % nx, y = u[2] + k / nx;
+            const int x = u[0] + kx, y = u[2] + ky;
             h0 = ok0 && x >= r0[0] && x <= r0[1] && y >= r0[2] && y <= r0[3];
             h1 = ok1 && x >= r1[0] && x <= r1[1] && y >= r1[2] && y <= r1[3];
             if (h0 || h1) tile = tile0 + (int64_t)y * tl.ntx + x;
@@ -195,7 +208,9 @@ __global__ void __launch_bounds__(256) k_tri_bin(const int4 *__restrict__ face_c
         unsigned my_rank = 0, lead_count = 0;
         while (pend) {
             const int leader = __ffsll((long long)pend) - 1;
-            const int64_t lead_tile = __shfl(tile, leader);
+            const int64_t lead_tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(tile >> 32), leader)
+                                                 << 32) |
+                                                (uint32_t)__builtin_amdgcn_readlane((int)tile, leader));
             const bool mine = tile == lead_tile;
             const unsigned long long m0 = __ballot(mine && h0), m1 = __ballot(mine && h1);
             if (mine) {
@@ -247,14 +262,59 @@ struct KeySetup {
     unsigned pad;
 };
 
+// Twice the oriented area of the triangle v, and its three edge tests over
+// the tile (see CovSetup), in an integer type T that holds their products;
+// returns true if an edge rejects the whole tile.
+template <class T>
+__device__ __forceinline__ T tri_area(const int4 (&v)[3]) {
+    return (T)(v[1].x - v[0].x) * (v[2].y - v[0].y) - (T)(v[1].y - v[0].y) * (v[2].x - v[0].x);
+}
+struct TriEdges {
+    int a0, b0, c0, a1, b1, c1, a2, b2, c2;
+    bool reject;
+};
+template <class T>
+__device__ __forceinline__ void edge_test(const int4 &p, const int4 &q, int ox, int oy, int ex, int ey, int &ea,
+                                          int &eb, int &ec, bool &reject) {
+    const int A = p.y - q.y, B = q.x - p.x;  // E(x,y) = A (x - px) + B (y - py)
+    const T Eo = (T)A * (ox - p.x) + (T)B * (oy - p.y);
+    const bool owned = (A > 0) || (A == 0 && B > 0);  // dy < 0, or dy == 0 and dx > 0
+    const T Eb = owned ? Eo : Eo - 1;
+    const T ax = (T)A * ex, by = (T)B * ey;
+    const T emin = Eb + min((T)0, ax) + min((T)0, by);
+    const T emax = Eb + max((T)0, ax) + max((T)0, by);
+    if (emax < 0) reject = true;
+    const bool all = emin >= 0;  // passes on the whole tile
+    ea = all ? 0 : A;
+    eb = all ? 0 : B;
+    ec = all ? 0 : (int)Eb;
+}
+template <class T>
+__device__ __forceinline__ TriEdges tri_edges(const int4 &v0, const int4 &v1, const int4 &v2, int ox, int oy, int ex,
+                                              int ey) {
+    TriEdges e;
+    e.reject = false;
+    edge_test<T>(v0, v1, ox, oy, ex, ey, e.a0, e.b0, e.c0, e.reject);
+    edge_test<T>(v1, v2, ox, oy, ex, ey, e.a1, e.b1, e.c1, e.reject);
+    edge_test<T>(v2, v0, ox, oy, ex, ey, e.a2, e.b2, e.c2, e.reject);
+    return e;
+}
+
 __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_t tri, int ox, int oy, int ex,
                                           int ey, CovSetup &cs) {
     const int4 *fs = fscr + 4 * (size_t)(tri >> 1);  // the face's four screen vertices
     const int t1 = (int)(tri & 1);
     int4 v[3] = {fs[0], fs[1 + t1], fs[2 + t1]};
     cs.pad0 = cs.pad1 = cs.pad2 = 0;
-    long long area = (long long)(v[1].x - v[0].x) * (v[2].y - v[0].y) -
-                     (long long)(v[1].y - v[0].y) * (v[2].x - v[0].x);
+    // Vertices within 2^13 sub-pixels of the tile origin (nearly every
+    // triangle) keep every product below in 32 bits: edge deltas below 2^14,
+    // offsets below 2^13, extents ex, ey below 2^9, so |E| < 2^28 + 2^24.
+    // The wave takes the 64-bit path only if one of its triangles needs it.
+    int reach = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) reach = max(reach, max(abs(v[k].x - ox), abs(v[k].y - oy)));
+    const bool narrow = !__any(!(reach < (1 << 13) && ex < (1 << 9) && ey < (1 << 9)));
+    long long area = narrow ? (long long)tri_area<int>(v) : tri_area<long long>(v);
     if (v[0].w < 0 || (v[1].w | v[2].w) || area == 0) {  // (culled triangles are never binned)
         cs.a0 = cs.b0 = cs.a1 = cs.b1 = cs.a2 = cs.b2 = 0;
         cs.c0 = -1;
@@ -267,28 +327,9 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
         v[2] = t;
         area = -area;
     }
-    int ea[3], eb[3], ec[3];
-    bool reject = false;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int4 p = v[k], q = v[(k + 1) % 3];
-        int A = p.y - q.y, B = q.x - p.x;  // E(x,y) = A (x - px) + B (y - py)
-        long long Eo = (long long)A * (ox - p.x) + (long long)B * (oy - p.y);
-        bool owned = (A > 0) || (A == 0 && B > 0);  // dy < 0, or dy == 0 and dx > 0
-        long long Eb = owned ? Eo : Eo - 1;
-        long long ax = (long long)A * ex, by = (long long)B * ey;
-        long long emin = Eb + min(0LL, ax) + min(0LL, by);
-        long long emax = Eb + max(0LL, ax) + max(0LL, by);
-        if (emax < 0) reject = true;
-        if (emin >= 0) {
-            ea[k] = eb[k] = 0;
-            ec[k] = 0;
-        } else {
-            ea[k] = A;
-            eb[k] = B;
-            ec[k] = (int)Eb;
-        }
-    }
+    const TriEdges e = narrow ? tri_edges<int>(v[0], v[1], v[2], ox, oy, ex, ey)
+                              : tri_edges<long long>(v[0], v[1], v[2], ox, oy, ex, ey);
+    bool reject = e.reject;
     // candidate pixels of the tile: centres inside the triangle's bounding box
     const int mnx = min(v[0].x, min(v[1].x, v[2].x)), mxx = max(v[0].x, max(v[1].x, v[2].x));
     const int mny = min(v[0].y, min(v[1].y, v[2].y)), mxy = max(v[0].y, max(v[1].y, v[2].y));
@@ -302,9 +343,9 @@ __device__ __forceinline__ void tri_setup(const int4 *__restrict__ fscr, uint32_
         cs.pad0 = 0;
         cs.pad1 = 0;
     } else {
-        cs.a0 = ea[0]; cs.b0 = eb[0]; cs.c0 = ec[0];
-        cs.a1 = ea[1]; cs.b1 = eb[1]; cs.c1 = ec[1];
-        cs.a2 = ea[2]; cs.b2 = eb[2]; cs.c2 = ec[2];
+        cs.a0 = e.a0; cs.b0 = e.b0; cs.c0 = e.c0;
+        cs.a1 = e.a1; cs.b1 = e.b1; cs.c1 = e.c1;
+        cs.a2 = e.a2; cs.b2 = e.b2; cs.c2 = e.c2;
         cs.pad0 = x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
         cs.pad1 = y1 - y0 + 1;
     }
