@@ -352,6 +352,10 @@ __device__ __forceinline__ bool shade_rounds(const ResolveArgs &a, const PixelRe
     return true;
 }
 
+// Keys (and triangle ids) a wave's LDS stash holds for lists of up to 64 R.
+template <int R>
+constexpr int STASH_KEYS = R <= 4 ? 256 : 64 * R;
+
 // Wavefront-scope ordering of a wave's LDS stash accesses (stores by some
 // lanes, loads by others) without a workgroup barrier.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -361,9 +365,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // List of pixel p (n <= 64 R): one wave, bitonic sort in registers.  Up to
-// 256 elements (R <= 4) the sorted keys go to `stash` (2 KB of LDS private to
-// the wave) for the shading rounds, so that they hold no registers across
-// the shading; longer lists keep them in registers.
+// 512 elements (R <= 8) the sorted keys go to `stash` (2 KB of LDS private to
+// the wave, 4 KB for R = 8) for the shading rounds, so that they hold no
+// registers across the shading; longer lists keep them in registers.
 template <int R>
 __device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint32_t p, uint32_t cnt, uint64_t first, int lane,
                                              uint32_t *__restrict__ stash) {
@@ -371,14 +375,19 @@ __device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint32_t p, u
     if (first + n > a.rec_cap) n = 0;  // overflowed workspace: records were not stored
     const uint64_t *src = a.rec + first;
     const PixelRef pr = pixel_ref(a.tl, p);
-    if constexpr (R <= 4) {
-        // Rendering only (no sorted export): sort 32-bit keys (depth << 8 |
-        // position in the list; depths stay below 2^24 - 1, so the padding ~0
-        // sorts last); the triangle ids stay in the stash at their list
-        // positions.  Equal depths must be ordered by triangle id, which these
-        // keys do not hold: the rounds stop short of the first such pair, and a
-        // pixel that needs fragments past it takes the 64-bit sort below.
-        uint32_t *skey = stash, *stri = stash + 256;
+    if constexpr (R <= 8) {
+        // Rendering only (no sorted export): sort 32-bit keys (depth << PB |
+        // position in the list, PB = 8 position bits up to 256 elements; for
+        // 512 the depth gives up its lowest bit to a ninth.  Depths stay below
+        // 2^24 - 1, so the padding ~0 sorts last: a list without padding has
+        // no key to collide with it); the triangle ids stay in the stash at
+        // their list positions.  Equal key depths must be ordered by depth and
+        // triangle id, which these keys do not hold: the rounds stop short of
+        // the first such pair, and a pixel that needs fragments past it takes
+        // the 64-bit sort below.
+        constexpr int PB = R <= 4 ? 8 : 9, DROP = PB - 8;
+        constexpr uint32_t PMASK = (1u << PB) - 1;
+        uint32_t *skey = stash, *stri = stash + STASH_KEYS<R>;
         if (!a.sorted_out) {
             if (!a.rgba) return;
             uint32_t key[R];
@@ -386,7 +395,7 @@ __device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint32_t p, u
             for (int r = 0; r < R; ++r) {
                 const uint32_t e = lane * R + r;
                 const uint64_t rec = e < n ? src[e] : ~0ull;
-                key[r] = e < n ? ((uint32_t)(rec >> 32) << 8) | e : ~0u;
+                key[r] = e < n ? (((uint32_t)(rec >> 32) >> DROP) << PB) | e : ~0u;
                 stri[e] = (uint32_t)rec;
             }
             bitonic_sort<R>(key, lane);
@@ -396,14 +405,14 @@ __device__ __forceinline__ void resolve_wave(const ResolveArgs &a, uint32_t p, u
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
-                const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
+                const bool t = (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> PB) == (nk >> PB);
                 const uint64_t b = __ballot(t);
                 if (b) tie = min(tie, (uint32_t)__builtin_ctzll(b) * R + r);
                 skey[lane * R + r] = key[r];
             }
             wave_lds_sync();
             const bool done = shade_rounds<R>(a, pr, n, lane, tie,
-                                              [&](int k) { return stri[skey[64u * k + lane] & 0xffu]; });
+                                              [&](int k) { return stri[skey[64u * k + lane] & PMASK]; });
             wave_lds_sync();  // (the stash is rewritten next)
             if (done) return;
         }
@@ -681,7 +690,7 @@ __global__ void __launch_bounds__(64) k_resolve_short(ClassWork w, ResolveArgs a
 // held to a register budget that keeps WAVES_R waves per SIMD resident.
 template <int R>
 __device__ __forceinline__ void resolve_waves(const ClassWork &w, const ResolveArgs &a) {
-    __shared__ uint32_t stash[RT / 64][R <= 4 ? 512 : 1];
+    __shared__ uint32_t stash[RT / 64][R <= 8 ? 2 * STASH_KEYS<R> : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t total = class_size(w);
     if (!total) return;
