@@ -28,10 +28,11 @@ namespace hexfc {
 // (m = 32), and the swizzle of the LDS crossbar for m = 4.
 __device__ __forceinline__ uint32_t xor_lane(uint32_t x, int m, int lane) {
     switch (m) {
-    case 1: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    case 2: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    // (every lane has a source in these patterns: no old value to keep)
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
     case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1f | (4 << 10));               // and 31, xor 4
-    case 8: return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);  // row_ror 8
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror 8
     case 16: {
         // rows 1, 3 of the first operand trade places with rows 0, 2 of the second
         const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
