@@ -898,6 +898,39 @@ __device__ __forceinline__ float4 head_composite(const ResolveArgs &a, const Pix
     return make_float4(lane0(H0), lane0(H1), lane0(H2), lane0(HA));
 }
 
+// Sorts the records v (element e = lane R + r, padding ~0) through 32-bit
+// keys (depth << 8 | list position: exact depths, up to 256 elements)
+// sorted in registers, the records gathered back from the wave's LDS stash
+// in key order.  A list with equal depths takes the 64-bit sort instead: its
+// order then depends on the triangle ids, which the keys do not hold.
+template <int R>
+__device__ __forceinline__ void sort_records(uint64_t (&v)[R], uint32_t n, int lane, uint64_t *__restrict__ rs) {
+    static_assert(R <= 4, "8 position bits");
+    wave_lds_sync();  // (the stash's previous use is over)
+    uint32_t key[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        rs[e] = v[r];
+        key[r] = e < n ? ((uint32_t)(v[r] >> 32) << 8) | e : ~0u;
+    }
+    bitonic_sort<R>(key, lane);
+    const uint32_t nxt = __shfl_down(key[0], 1);
+    bool tie = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t nk = r + 1 < R ? key[r + 1] : nxt;
+        tie |= (r + 1 < R || lane < 63) && lane * R + r + 1 < n && (key[r] >> 8) == (nk >> 8);
+    }
+    if (__any(tie)) {
+        bitonic_sort<R>(v, lane);  // (v is unchanged so far)
+        return;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = key[r] == ~0u ? ~0ull : rs[key[r] & 0xffu];
+}
+
 template <int R, int MODE>
 __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restrict__ list, uint32_t npix, int K,
                                                        float conf_min, ResolveArgs a, float *__restrict__ head,
@@ -926,8 +959,9 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     const int64_t o = out_base + wave;
     float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
     bool have_head = false;
+    // (the head selection's stash, then the 32-bit sort's record stash)
+    __shared__ uint64_t stash[4][MODE == TAIL_RESOLVE ? (R <= 2 ? 128 : 64 * R) : 1];
     if constexpr (MODE == TAIL_RESOLVE) {
-        __shared__ uint64_t stash[4][128];
         uint64_t hk;
         const uint32_t m = wave_head<R, 64>(v, n, K, lane, stash[threadIdx.x >> 6], hk);
         const float4 h = head_composite(a, pr, hk, m, lane);
@@ -948,7 +982,10 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         HA = h.w;
         have_head = true;
     }
-    bitonic_sort<R>(v, lane);
+    if constexpr (MODE == TAIL_RESOLVE && R <= 4)
+        sort_records<R>(v, n, lane, stash[threadIdx.x >> 6]);
+    else
+        bitonic_sort<R>(v, lane);
     if (!have_head) {
         // head: sorted element l to lane l, one exact shade per lane
         uint64_t hv = ~0ull;
