@@ -629,24 +629,39 @@ __global__ void __launch_bounds__(RASTER_WG) k_fill(Tiling tl, const uint64_t *_
     // the group's first slot per pixel (the fragments of the groups before it, from the count pass)
     s_pos[grp][t] = gpre[(size_t)g * RASTER_WG + threadIdx.x];
     __syncthreads();
-    // expand each batch into fragments, one lane per fragment
+    // expand each batch into fragments, one lane per fragment; a lane's bin
+    // entry and masks for the next batch are loaded while this one is worked
+    // on (its triangle's screen vertices too measured slower: registers)
+    uint32_t bin = 0;
+    uint64_t mk[NW];
+    auto load_entry = [&](int it2) {
+        const uint64_t b = batch_base<NT, S>(ch, it2) + t;
+        if (it2 < ch.iters && b < ch.b1) {
+            bin = bins[b];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mk[w] = masks[b * NW + w];
+        }
+    };
+    load_entry(0);
     for (int it = 0; it < ch.iters; ++it) {
         const uint64_t base = batch_base<NT, S>(ch, it);
         const int m = base < ch.b1 ? (int)min((uint64_t)NT, ch.b1 - base) : 0;
         uint32_t c = 0;
+        uint32_t tri = 0;
         if (t < m) {
+            tri = bin;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                const uint64_t mk = masks[(base + t) * NW + w];
-                s_mask[grp][t * NW + w] = mk;
-                c += (uint32_t)__popcll(mk);
-            }
-            if (c) {  // (a covered triangle is not culled: its area is not zero)
-                KeySetup ks;
-                key_setup(fscr, bins[base + t], ox, oy, ks);
-                s_key[grp][t] = ks;
+                s_mask[grp][t * NW + w] = mk[w];
+                c += (uint32_t)__popcll(mk[w]);
             }
         }
+        if (c) {  // (a covered triangle is not culled: its area is not zero)
+            KeySetup ks;
+            key_setup(fscr, tri, ox, oy, ks);
+            s_key[grp][t] = ks;
+        }
+        load_entry(it + 1);
         // exclusive scan of the entries' fragment counts over the group
         uint32_t incl = c;
 #pragma unroll
