@@ -148,14 +148,17 @@ struct PixelRef {
     int x, y;
 };
 __device__ __forceinline__ PixelRef pixel_ref(const Tiling &tl, uint32_t gp) {
-    const int TP = tl.TW * tl.TH;
-    const int64_t pt = (int64_t)tl.ntiles * TP;
+    // (tile sides are powers of two; the views' pixels count below 2^32, as their ids do)
+    const int sw = __builtin_ctz((unsigned)tl.TW), sh = __builtin_ctz((unsigned)tl.TH), sp = sw + sh;
+    const uint32_t pt = (uint32_t)tl.ntiles << sp;
     PixelRef r;
-    r.view = gp / pt;
-    const int64_t p = gp - r.view * pt;
-    const int tile = (int)(p / TP), l = (int)(p % TP);
-    r.x = (tile % tl.ntx) * tl.TW + l % tl.TW;
-    r.y = (tile / tl.ntx) * tl.TH + l / tl.TW;
+    const uint32_t view = gp / pt;
+    const uint32_t p = gp - view * pt;
+    const uint32_t tile = p >> sp, l = p & ((1u << sp) - 1u);
+    const uint32_t ty = tile / (uint32_t)tl.ntx, tx = tile - ty * (uint32_t)tl.ntx;
+    r.view = view;
+    r.x = (int)((tx << sw) + (l & (uint32_t)(tl.TW - 1)));
+    r.y = (int)((ty << sh) + (l >> sw));
     return r;
 }
 
