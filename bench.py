@@ -86,7 +86,7 @@ KERNEL_SYMBOL = {"fill": "hexfc::k_fill<8, 8>", "count": "hexfc::k_count<8, 8>",
 def measured_traffic(kernel: str):
     """Bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, scaled by the copy calibration; None when there is no
-    summary for it or the kernel's source changed since it was taken."""
+    summary for it or the kernel's sources changed since it was taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_bent128_1080p.md")
@@ -98,8 +98,11 @@ def measured_traffic(kernel: str):
         kv = dict(x.split("=", 1) for x in line.split()[1:])
         if kv.get("kernel") != kernel:
             continue
-        src = os.path.join(ROOT, kv["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["sha256"]:
+        # (the kernel's sources, joined by '+', hashed over their concatenation)
+        srcs = [os.path.join(ROOT, f) for f in kv["source"].split("+")]
+        if not all(os.path.exists(f) for f in srcs):
+            return None
+        if hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest() != kv["sha256"]:
             return None
         return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
                          float(kv["write_kib"]) * float(kv["write_scale"]))
