@@ -729,11 +729,13 @@ hexfc_status learned_checks(hexfc_ctx *ctx, const hexfc_hotspot *hot, const hexf
 void enqueue_tail_features(hexfc_ctx *ctx, const ResolveArgs &a, int K, float *head, float *feat, float *target,
                            uint32_t *pix, bool rowmajor, float conf_min, uint8_t *mask, hipStream_t s) {
     ScopedTimer tm(ctx, s, KID_TAIL);
+    launch_zero_u32(ctx->rqueue.as<uint32_t>(), NCLASS * QUEUE_SEGS * QUEUE_STRIDE, s);  // the classes' work queues
     int64_t base = 0;
     for (int c = 1; c < NCLASS - 1; ++c) {
         const uint32_t nc = (uint32_t)ctx->last_stats[ST_CLASS + c];
-        launch_tail_features(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap, nc, K, a, head, feat, target, pix,
-                             rowmajor, base, conf_min, mask, s);
+        launch_tail_features(c, ctx->cls.as<uint32_t>() + (int64_t)c * ctx->cls_cap, nc,
+                             ctx->rqueue.as<uint32_t>() + c * QUEUE_SEGS * QUEUE_STRIDE, K, a, head, feat, target,
+                             pix, rowmajor, base, conf_min, mask, s);
         base += nc;
     }
 }

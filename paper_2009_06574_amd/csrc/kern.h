@@ -288,10 +288,11 @@ constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)(NOALLOC_MAX_ROWS * LEARNED_ROW
 // pix_out receives the global tile-major pixel id, or with rowmajor the
 // image index (view * H + y) * W + x.  With a.rgba set (the learned resolve)
 // a pixel whose head is opaque to within 2^-20 and at least conf_min gets
-// its final colour here (mask 0) and pix_out PIX_SKIP.
-void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a,
-                          float *head, float *feat, float *target, uint32_t *pix_out, bool rowmajor,
-                          int64_t out_base, float conf_min, uint8_t *mask, hipStream_t s);
+// its final colour here (mask 0) and pix_out PIX_SKIP.  queue: the class's
+// QUEUE_SEGS work-queue counters, zero at the launch.
+void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, uint32_t *queue, int K,
+                          const ResolveArgs &a, float *head, float *feat, float *target, uint32_t *pix_out,
+                          bool rowmajor, int64_t out_base, float conf_min, uint8_t *mask, hipStream_t s);
 
 // Silhouettes of the boundary surface: per pixel of the pass's tiles
 // (device range pass_tiles[0..1]; the grid covers the nv views' tiles) the

@@ -931,17 +931,16 @@ __device__ __forceinline__ void sort_records(uint64_t (&v)[R], uint32_t n, int l
     for (int r = 0; r < R; ++r) v[r] = key[r] == ~0u ? ~0ull : rs[key[r] & 0xffu];
 }
 
+// Row `item` of a class list: one wave.  `stash` is the wave's LDS (head
+// selection, then the 32-bit sort's records).
 template <int R, int MODE>
-__global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restrict__ list, uint32_t npix, int K,
-                                                       float conf_min, ResolveArgs a, float *__restrict__ head,
-                                                       float *__restrict__ feat, float *__restrict__ target,
-                                                       uint32_t *__restrict__ pix_out, uint8_t *__restrict__ mask,
-                                                       bool rowmajor, int64_t out_base) {
+__device__ __forceinline__ void tail_item(uint32_t item, const uint32_t *__restrict__ list, int K, float conf_min,
+                                          const ResolveArgs &a, float *__restrict__ head, float *__restrict__ feat,
+                                          float *__restrict__ target, uint32_t *__restrict__ pix_out,
+                                          uint8_t *__restrict__ mask, bool rowmajor, int64_t out_base,
+                                          uint64_t *__restrict__ stash, int lane) {
     constexpr bool TRAIN = MODE == TAIL_TRAIN;
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (wave >= npix) return;
-    const uint32_t p = list[wave];
+    const uint32_t p = list[item];
     uint32_t n = min(a.count[p], (uint32_t)(64 * R));
     const uint64_t first = a.off[p] - rec_base(a);
     if (first + n > a.rec_cap) n = 0;
@@ -956,14 +955,12 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
     const ViewParams &vp = view_params(a.views, pr.view);
     const ShadeParams &sp = vp.sp;
     const VertRec *vert = a.mesh.vert + pr.view * a.mesh.V;
-    const int64_t o = out_base + wave;
+    const int64_t o = out_base + item;
     float H0 = 0.f, H1 = 0.f, H2 = 0.f, HA = 0.f;
     bool have_head = false;
-    // (the head selection's stash, then the 32-bit sort's record stash)
-    __shared__ uint64_t stash[4][MODE == TAIL_RESOLVE ? (R <= 2 ? 128 : 64 * R) : 1];
     if constexpr (MODE == TAIL_RESOLVE) {
         uint64_t hk;
-        const uint32_t m = wave_head<R, 64>(v, n, K, lane, stash[threadIdx.x >> 6], hk);
+        const uint32_t m = wave_head<R, 64>(v, n, K, lane, stash, hk);
         const float4 h = head_composite(a, pr, hk, m, lane);
         if (n > (uint32_t)K && 1.f - h.w < T_EPS && h.w >= conf_min) {
             // the tail is invisible: final colour now, no row for the network
@@ -983,7 +980,7 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         have_head = true;
     }
     if constexpr (MODE == TAIL_RESOLVE && R <= 4)
-        sort_records<R>(v, n, lane, stash[threadIdx.x >> 6]);
+        sort_records<R>(v, n, lane, stash);
     else
         bitonic_sort<R>(v, lane);
     if (!have_head) {
@@ -1059,6 +1056,26 @@ __global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restric
         if (TRAIN) reinterpret_cast<float4 *>(target)[o] = make_float4(T0, T1, T2, TA);
         pix_out[o] = rowmajor ? (uint32_t)((pr.view * a.tl.H + pr.y) * a.tl.W + pr.x) : p;
     }
+}
+
+// The rows of one length class on a resident grid: the waves drain the
+// class list through its queue counters (zeroed before the launch), as the
+// exact resolve's class kernels do.
+template <int R, int MODE>
+__global__ void __launch_bounds__(256) k_tail_features(const uint32_t *__restrict__ list, uint32_t npix,
+                                                       uint32_t *__restrict__ queue, int K, float conf_min,
+                                                       ResolveArgs a, float *__restrict__ head,
+                                                       float *__restrict__ feat, float *__restrict__ target,
+                                                       uint32_t *__restrict__ pix_out, uint8_t *__restrict__ mask,
+                                                       bool rowmajor, int64_t out_base) {
+    __shared__ uint64_t stash[4][MODE == TAIL_RESOLVE ? (R <= 2 ? 128 : 64 * R) : 1];
+    const int lane = threadIdx.x & 63;
+    if (!npix) return;
+    drain<R == 1 ? 4 : R == 2 ? 2 : 1, 64>(npix, queue, lane, [&](uint32_t item) {
+        wave_lds_sync();  // (the wave's stash is reused item after item)
+        tail_item<R, MODE>(item, list, K, conf_min, a, head, feat, target, pix_out, mask, rowmajor, out_base,
+                           stash[threadIdx.x >> 6], lane);
+    });
 }
 
 // ------------------------------------------------------------------ silhouettes
@@ -1534,26 +1551,27 @@ void launch_resolve_approx(int cls, const uint32_t *pix_list, uint32_t npix, int
 #undef APPROX
 }
 
-void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int K, const ResolveArgs &a, float *head,
-                          float *feat, float *target, uint32_t *pix_out, bool rowmajor, int64_t out_base,
-                          float conf_min, uint8_t *mask, hipStream_t s) {
+void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, uint32_t *queue, int K,
+                          const ResolveArgs &a, float *head, float *feat, float *target, uint32_t *pix_out,
+                          bool rowmajor, int64_t out_base, float conf_min, uint8_t *mask, hipStream_t s) {
     if (npix == 0) return;
-    dim3 g((npix + 3) / 4);
     // learned resolve (an output image), training rows (a target) or feature rows
     const int mode = a.rgba ? TAIL_RESOLVE : target ? TAIL_TRAIN : TAIL_FEATURES;
-#define TAIL(RV)                                                                                                   \
-    switch (mode) {                                                                                                \
-        case TAIL_RESOLVE:                                                                                         \
-            k_tail_features<RV, TAIL_RESOLVE><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat, target, \
-                                                                pix_out, mask, rowmajor, out_base);                \
-            break;                                                                                                 \
-        case TAIL_TRAIN:                                                                                           \
-            k_tail_features<RV, TAIL_TRAIN><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat, target,   \
-                                                              pix_out, mask, rowmajor, out_base);                  \
-            break;                                                                                                 \
-        default:                                                                                                   \
-            k_tail_features<RV, TAIL_FEATURES><<<g, 256, 0, s>>>(pix_list, npix, K, conf_min, a, head, feat,       \
-                                                                 target, pix_out, mask, rowmajor, out_base);       \
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    // a resident grid (the device's workgroups of the kernel, once per kernel), at most a wave per row
+    auto grid = [&](int resident_blocks) { return dim3((unsigned)std::min<uint64_t>(resident_blocks, (npix + 3) / 4)); };
+#define TAIL_LAUNCH(RV, MV)                                                                                    \
+    {                                                                                                          \
+        static const int res = resident(dev, k_tail_features<RV, MV>, 256);                                    \
+        k_tail_features<RV, MV><<<grid(res), 256, 0, s>>>(pix_list, npix, queue, K, conf_min, a, head, feat, \
+                                                           target, pix_out, mask, rowmajor, out_base);         \
+    }
+#define TAIL(RV)                                                        \
+    switch (mode) {                                                     \
+        case TAIL_RESOLVE: TAIL_LAUNCH(RV, TAIL_RESOLVE) break;         \
+        case TAIL_TRAIN: TAIL_LAUNCH(RV, TAIL_TRAIN) break;             \
+        default: TAIL_LAUNCH(RV, TAIL_FEATURES)                         \
     }
     switch (cls) {
         case 1: TAIL(1); break;
@@ -1565,6 +1583,7 @@ void launch_tail_features(int cls, const uint32_t *pix_list, uint32_t npix, int 
         default: break;
     }
 #undef TAIL
+#undef TAIL_LAUNCH
 }
 
 }  // namespace hexfc
