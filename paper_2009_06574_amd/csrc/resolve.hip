@@ -257,6 +257,23 @@ __device__ __forceinline__ void resolve_lane(const ResolveArgs &a, uint64_t base
     }
 }
 
+// One stage of the bitonic network within the lanes' registers: partners r
+// and r | J (J < R, a constant: the registers stay statically indexed).
+template <int J, int R, class K>
+__device__ __forceinline__ void bitonic_inlane(K (&v)[R], int lane, int k) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if ((r & J) == 0) {
+            const int r2 = r | J;
+            const bool up = ((lane * R + r) & k) == 0;
+            const K x = v[r], y = v[r2];
+            const bool sw = up ? (x > y) : (x < y);
+            v[r] = sw ? y : x;
+            v[r2] = sw ? x : y;
+        }
+    }
+}
+
 // Element e = lane*R + r of the padded list lives in register v[r] of `lane`.
 template <int R, class K>
 __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
@@ -274,7 +291,7 @@ __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
                     const bool up = ((lane * R + r) & k) == 0;
                     v[r] = (lower == up) ? (v[r] < o ? v[r] : o) : (v[r] < o ? o : v[r]);
                 }
-            } else {
+            } else if constexpr (R < 32) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if ((r & j) == 0) {
@@ -285,6 +302,17 @@ __device__ __forceinline__ void bitonic_sort(K (&v)[R], int lane) {
                         v[r] = sw ? y : x;
                         v[r2] = sw ? x : y;
                     }
+                }
+            } else {
+                // (32 registers: the stage loops stay rolled, so j is not a
+                // constant here; a register index from it would put v in
+                // private memory)
+                switch (j) {
+                    case 1: bitonic_inlane<1>(v, lane, k); break;
+                    case 2: bitonic_inlane<2>(v, lane, k); break;
+                    case 4: bitonic_inlane<4>(v, lane, k); break;
+                    case 8: bitonic_inlane<8>(v, lane, k); break;
+                    default: bitonic_inlane<16>(v, lane, k); break;
                 }
             }
         }
