@@ -1047,7 +1047,7 @@ __device__ __forceinline__ void tail_item(uint32_t item, const uint32_t *__restr
         }
         const float4 fp = a.mesh.face_px[tri >> 1];
         const float dx = fp.x - sp.hc[0], dy = fp.y - sp.hc[1], dz = fp.z - sp.hc[2];
-        const float dist = fminf(sqrtf(dx * dx + dy * dy + dz * dz) * sp.inv_r, 1.f);
+        const float dist = fminf(__builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz) * sp.inv_r, 1.f);
         const float d2 = dist * dist;
         const float al = (sp.a_lo + (sp.a_hi - sp.a_lo) * fp.w) * d2 * d2;
         const float key = (float)(KMAX - (uint32_t)(v[r] >> 32));
